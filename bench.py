@@ -1,0 +1,231 @@
+"""Benchmark of the extruded-prism DG tracer step on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+
+Workload: 199,712 jittered triangles x 30 sigma layers (5,991,360 prisms),
+4 advected fields (u, v, temperature, salinity), FP64; synthetic seeded
+inputs already resident in HBM.  A step is three fused SSP-RK3 stages (volume
+quadrature + upwind lateral/vertical fluxes + M^-1 + stage combination) and
+one FP64 implicit vertical-diffusion column solve.
+
+``value`` = prism-node DOF updates per second per RK stage over whole steps:
+3 * 6 * P * F / t_step (the column solve's time is included).  The stage
+kernel's own rate and its HBM roofline fraction are reported beside it, with
+the same measurement for the FP32-state / FP64-solve form, and the FP64 CPU
+oracle timed on a bounded sample on the host.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "prism-node DOF updates/sec per RK stage + HBM GB/s (FP32 vs FP64, 1 GPU)"
+HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(P, C, n_lev, F, es, stage, w_zero=True):
+    """Algorithmic HBM bytes of one fused stage launch: read the stage input
+    (6F values per prism), T^n (6F, stages 1-2), nodal u, v (12; w skipped
+    when zero), the level heights (3 per level) and the 2D column data (6
+    vertex coordinates + 3 neighbour indices per column); write 6F."""
+    vals = (6 * F + (6 * F if stage > 0 else 0) + 12 + (0 if w_zero else 6) + 6 * F) * P + 3 * n_lev
+    return vals * es + C * (6 * es + 12)
+
+
+def solve_bytes(P, C, n_lev, F, es):
+    """Read T* (6F per prism) and the levels, write the solution (6F)."""
+    return (12 * F * P + 3 * n_lev) * es + C * 8
+
+
+def time_calls(torch, fn, reps):
+    """Average duration of fn() over reps calls, HIP events on the current stream."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def run_gpu(w, precision, steps, warmup, torch, P_mod):
+    s, U, kappa, state = P_mod.from_workload(w, precision)
+    torch.cuda.synchronize()
+    P, C, F = w.n_prisms, w.n_cols, w.n_fields
+    n_lev = P + C
+    es = 8 if precision == P_mod.SDG_FP64 else 4
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    t_step = (t1 - t0) / steps
+    # per-kernel durations (same stream), buffers as in sdg_step
+    A, B = s.new_state(), s.new_state()
+    reps = 10
+    t_st = [time_calls(torch, lambda: s.rk_stage(0, None, state, A), reps),
+            time_calls(torch, lambda: s.rk_stage(1, state, A, B), reps),
+            time_calls(torch, lambda: s.rk_stage(2, state, B, A), reps)]
+    t_sv = time_calls(torch, lambda: s.vertical_implicit_solve(A, B), reps)
+    by = [stage_bytes(P, C, n_lev, F, es, k) for k in range(3)]
+    sb = solve_bytes(P, C, n_lev, F, es)
+    stage_gbs = sum(by) / sum(t_st)
+    res = {
+        "t_step": t_step,
+        "value": 3 * 6 * P * F / t_step,
+        "t_stage": [float(x) for x in t_st],
+        "t_solve": float(t_sv),
+        "stage_rate": 6 * P * F / (sum(t_st) / 3),
+        "stage_GBps": stage_gbs / 1e9,
+        "stage_bytes_per_launch": [int(b) for b in by],
+        "solve_GBps": sb / t_sv / 1e9,
+        "solve_bytes_per_launch": int(sb),
+    }
+    del s, U, kappa, state, A, B
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The FP64 oracle, single-threaded BLAS, on a bounded sample: RK stages
+    on a block of prisms and column solves on a block of columns; scaled to
+    DOF-stage updates per second over whole steps."""
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    t_build = time.perf_counter()
+    m = O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
+    t_build = time.perf_counter() - t_build
+    F = w.n_fields
+    n_pr = 1 << 16
+    prisms = np.arange(n_pr)
+    t0 = time.perf_counter()
+    O.rk_stage(m, w.U, 1, w.T0, w.T0, w.dt, w.t_ext, prisms=prisms)
+    t_stage = (time.perf_counter() - t0) / n_pr                 # s per prism-stage
+    n_col = 512
+    t0 = time.perf_counter()
+    O.implicit_solve(m, w.kappa, w.dt, w.T0, w.penalty, columns=np.arange(n_col))
+    t_solve = (time.perf_counter() - t0) / (n_col * int(w.nlayers[0]))   # s per prism
+    if limiter is not None:
+        limiter.unregister()
+    per_prism_step = 3 * t_stage + t_solve
+    return {
+        "value": 18 * F / per_prism_step,
+        "unit": "DOF-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one RK stage on {n_pr} prisms and the column solve on {n_col} columns "
+                  f"({n_col * int(w.nlayers[0])} prisms) of the same workload, FP64 NumPy, BLAS limited "
+                  f"to 1 thread; host has {os.cpu_count()} logical CPUs; mesh view build {t_build:.1f} s excluded",
+        "stage_rate": 6 * F / t_stage,
+        "s_per_prism_stage": t_stage,
+        "s_per_prism_solve": t_solve,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--n", type=int, default=316, help="split squares per side (316: 199,712 triangles)")
+    ap.add_argument("--layers", type=int, default=30)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU column "
+              f"decomposition is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_16082_amd as P_mod
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    P_mod.load_library()
+    t0 = time.perf_counter()
+    w = W.config2(n=args.n, n_layers=args.layers)
+    log(f"workload built in {time.perf_counter() - t0:.1f} s: {w.n_cols} columns, {w.n_prisms} prisms, "
+        f"{w.n_fields} fields")
+    r64 = run_gpu(w, P_mod.SDG_FP64, args.steps, args.warmup, torch, P_mod)
+    log("fp64", json.dumps(r64))
+    r32 = None
+    if not args.no_fp32:
+        r32 = run_gpu(w, P_mod.SDG_FP32_STATE_FP64_SOLVE, args.steps, args.warmup, torch, P_mod)
+        log("fp32 state / fp64 solve", json.dumps(r32))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+        log("cpu", json.dumps(cpu))
+
+    out = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["t_step"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.n_cols} jittered triangles x {args.layers} sigma layers "
+                        f"({w.n_prisms} prisms), 4 advected fields, FP64, SSP-RK3 + FP64 vertical solve",
+            "prisms": w.n_prisms,
+            "fields": w.n_fields,
+            "dof_per_field": 6 * w.n_prisms,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "stage_kernel (fused rhs + SSP-RK3 stage), mean of the 3 stage launches",
+            "achieved": r64["stage_GBps"],
+            "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s",
+            "frac": r64["stage_GBps"] * 1e9 / HBM_PEAK,
+            "traffic": None,
+        },
+        "kernels_fp64": {
+            "t_stage_s": r64["t_stage"], "t_solve_s": r64["t_solve"],
+            "stage_rate": r64["stage_rate"], "solve_GBps": r64["solve_GBps"],
+            "stage_bytes_per_launch": r64["stage_bytes_per_launch"],
+            "solve_bytes_per_launch": r64["solve_bytes_per_launch"],
+        },
+        "cpu_baseline": cpu,
+    }
+    if r32 is not None:
+        out["fp32_state_fp64_solve"] = {
+            "value": r32["value"], "ms_per_step": r32["t_step"] * 1e3,
+            "speedup_vs_fp64": r32["value"] / r64["value"],
+            "t_stage_s": r32["t_stage"], "t_solve_s": r32["t_solve"],
+            "stage_rate": r32["stage_rate"], "stage_GBps": r32["stage_GBps"],
+            "stage_frac": r32["stage_GBps"] * 1e9 / HBM_PEAK, "solve_GBps": r32["solve_GBps"],
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

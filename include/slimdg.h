@@ -1,0 +1,196 @@
+/*
+ * slimdg.h -- C ABI of the MI355X (gfx950) nodal-P1 DG tracer operator on
+ * extruded prism meshes.
+ *
+ * The operator (paper, section 1.1 tracer equation; section 2.2 stage
+ * equations and their explicit variant; section 2.4 column systems):
+ *
+ *   dT/dt + div_h(u T) + d(w T)/dz = d/dz(kappa dT/dz)
+ *
+ * on a triangle mesh extruded into columns of linear prisms.  Per field and
+ * prism there are six nodal values: the three top-face nodes then the three
+ * bottom-face nodes (the node split of Algorithm 1).
+ *
+ *   rhs_3d                   L(T) = M^-1 R(T): volume quadrature plus upwind
+ *                            lateral and horizontal interface fluxes, then the
+ *                            element-local inverse of the block-diagonal mass
+ *                            matrix (explicit variant of the stage equation).
+ *   rk_stage                 one SSP-RK3 stage, Tout = a Tn + b (Ts + dt L(Ts)),
+ *                            (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3).
+ *   vertical_implicit_solve  (M - dt A) Tout = M T* per column, A the interior-
+ *                            penalty vertical diffusion operator; block
+ *                            tridiagonal with 6x6 blocks whose off-diagonal
+ *                            blocks have the half-block sparsity of section 2.4;
+ *                            always computed in FP64.
+ *   step                     three rk_stage calls then one vertical solve.
+ *   mass                     m_f = sum_K 1^T M_K T_K, FP64, per member and field.
+ *
+ * Storage layout ("cell layout", the paper's section 2.1.1 grouping of
+ * columns, here with 64 columns per cell -- one wavefront): columns keep the
+ * caller's triangle order and are grouped in cells of 64 consecutive
+ * columns; cell k is as deep as its deepest column, D_k.  The prism of column
+ * c, layer l (0 = surface) lives in slot
+ *
+ *     cell_base[c / 64] + l * 64 + (c % 64),   cell_base[k] = 64 * sum_{j<k} D_j,
+ *
+ * and every nodal array is [component][node 0..5][slot] with n_slots slots
+ * (sdg_layout.n_slots).  Slots of padding (l >= nlayers[c], or columns past
+ * the last triangle) are never read and never written.  sdg_prism_slots()
+ * returns the slot of every prism in natural order (column by column, layers
+ * top to bottom) so callers can scatter and gather.
+ *
+ * Ownership: the library never allocates device memory.  The caller provides
+ * one workspace buffer (sdg_layout.workspace_bytes) at mesh upload; state,
+ * velocity, diffusivity and outputs are caller-owned device buffers.  Device
+ * pointers given to sdg_set_velocity / sdg_set_diffusivity / sdg_set_fields
+ * are borrowed until replaced; the caller keeps them alive.
+ *
+ * Execution: every call enqueues on the stream given to sdg_create (NULL =
+ * the default stream) and returns without synchronising, except
+ * sdg_mesh_upload, sdg_mass and sdg_sync.  Argument, mesh and workspace
+ * errors are reported synchronously; asynchronous kernel errors surface at
+ * sdg_sync or sdg_mass.  No C++ exception crosses the ABI.  A context is used
+ * by one host thread at a time.
+ *
+ * Precision: SDG_FP64 -- state, velocity and fluxes in double; SDG_FP32 --
+ * state, velocity, geometry and fluxes in float, vertical solve in FP64;
+ * SDG_FP32_STATE_FP64_SOLVE is the same as SDG_FP32 (named for the precision
+ * form: FP32 state and fluxes, FP64 column solve and mass sums).  kappa and
+ * the mass sums are always double.
+ */
+#ifndef SLIMDG_H
+#define SLIMDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDG_ABI_VERSION 1
+#define SDG_CELL_COLUMNS 64
+#define SDG_MAX_FIELDS 4
+
+typedef enum {
+  SDG_OK = 0,
+  SDG_E_ARG = -1,         /* bad argument (null pointer, out-of-range value) */
+  SDG_E_MESH = -2,        /* mesh description fails validation */
+  SDG_E_HIP = -3,         /* HIP runtime error (message has the HIP string) */
+  SDG_E_STATE = -4,       /* call made before the state it needs was set */
+  SDG_E_UNSUPPORTED = -5, /* valid request this build does not support */
+  SDG_E_NUMERIC = -6,     /* non-finite values found (check_finite) */
+  SDG_E_WORKSPACE = -7    /* workspace too small or misaligned */
+} sdg_status;
+
+typedef enum {
+  SDG_FP64 = 0,
+  SDG_FP32 = 1,
+  SDG_FP32_STATE_FP64_SOLVE = 2
+} sdg_precision;
+
+typedef struct sdg_ctx sdg_ctx; /* opaque */
+
+/* Mesh description.  All pointers are HOST pointers, read during the call
+ * (query, slots, upload) and not retained. */
+typedef struct {
+  int32_t n_members;              /* >= 1; members are disjoint meshes */
+  int32_t n_tri;                  /* columns, all members concatenated */
+  int32_t n_vert;
+  const int32_t* member_tri_off;  /* [n_members+1] column offsets; NULL = one member */
+  const double* vxy;              /* [n_vert][2] vertex coordinates [m] */
+  const int32_t* tri;             /* [n_tri][3] vertex ids, counter-clockwise */
+  const int32_t* nbr;             /* [n_tri][3]; edge k = (tri[k] -> tri[(k+1)%3]);
+                                     neighbour column or -1 (open boundary) */
+  const int32_t* nlayers;         /* [n_tri], >= 1 */
+  const double* zlev;             /* per column (nlayers+1) levels x 3 vertex heights,
+                                     top level first, columns concatenated [m] */
+  int32_t n_fields;               /* 1 .. SDG_MAX_FIELDS */
+  int32_t precision;              /* sdg_precision */
+} sdg_mesh_desc;
+
+typedef struct {
+  int64_t n_prisms;        /* live prisms = sum(nlayers) */
+  int64_t n_slots;         /* slots per nodal array (>= n_prisms) */
+  int32_t n_cells;
+  int32_t max_layers;
+  int32_t n_fields;
+  int32_t state_elem_bytes;   /* 8 (FP64) or 4 */
+  size_t state_bytes;         /* bytes of one [n_fields][6][n_slots] state array */
+  size_t velocity_bytes;      /* bytes of one [3][6][n_slots] velocity array */
+  size_t workspace_bytes;     /* device workspace for sdg_mesh_upload */
+} sdg_layout;
+
+typedef struct {
+  double dt;               /* time step [s], > 0 */
+  double penalty_eta;      /* interior-penalty factor (4 if <= 0 is given) */
+  const double* t_ext;     /* HOST [n_fields] exterior values on open boundaries; NULL = 0 */
+  int32_t w_is_zero;       /* 1: the vertical velocity component is not read */
+  int32_t check_finite;    /* 1: sdg_step checks the state after its last step */
+} sdg_params;
+
+int sdg_abi_version(void);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* sdg_last_error(void);
+
+/* Validate a mesh description and report sizes.  Host only; no GPU needed.
+ * SDG_E_ARG / SDG_E_MESH with a message on failure. */
+sdg_status sdg_query_layout(const sdg_mesh_desc* mesh, sdg_layout* out);
+
+/* Slot of each prism in natural order: host_slots[off[c] + l] for column c,
+ * layer l, where off is the prefix sum of nlayers.  host_slots has
+ * n_prisms entries.  Host only. */
+sdg_status sdg_prism_slots(const sdg_mesh_desc* mesh, int64_t* host_slots);
+
+/* Create a context on HIP device `device`; `hip_stream` (a hipStream_t) is
+ * borrowed, NULL = default stream. */
+sdg_status sdg_create(sdg_ctx** out, int device, void* hip_stream);
+sdg_status sdg_destroy(sdg_ctx* ctx);
+
+/* Validate, lay out and copy the mesh into the caller's device workspace
+ * (>= workspace_bytes, 256-byte aligned), then compute the per-column
+ * geometry on the device.  Synchronises the stream.  Any previously set
+ * velocity / diffusivity / fields are forgotten. */
+sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_workspace,
+                           size_t workspace_bytes);
+
+sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* params);
+
+/* Nodal velocity [3][6][n_slots] (u, v, w) in the state precision. */
+sdg_status sdg_set_velocity(sdg_ctx* ctx, const void* dev_uvw);
+
+/* Vertical diffusivity per layer index, [max_layers] doubles [m^2/s]. */
+sdg_status sdg_set_diffusivity(sdg_ctx* ctx, const double* dev_kappa);
+
+/* State advanced in place by sdg_step, [n_fields][6][n_slots]. */
+sdg_status sdg_set_fields(sdg_ctx* ctx, void* dev_state);
+
+/* dev_L = M^-1 R(dev_T).  Needs velocity and params.  dev_L must not alias dev_T. */
+sdg_status sdg_rhs_3d(sdg_ctx* ctx, const void* dev_T, void* dev_L);
+
+/* dev_Tout = a dev_Tn + b (dev_Ts + dt L(dev_Ts)) for stage 0, 1, 2.
+ * Stage 0 does not read dev_Tn.  dev_Tout must not alias dev_Ts or dev_Tn. */
+sdg_status sdg_rk_stage(sdg_ctx* ctx, int stage, const void* dev_Tn, const void* dev_Ts,
+                        void* dev_Tout);
+
+/* (M - dt A) dev_Tout = M dev_Tstar per column.  Needs diffusivity and
+ * params.  dev_Tout may alias dev_Tstar. */
+sdg_status sdg_vertical_implicit_solve(sdg_ctx* ctx, const void* dev_Tstar, void* dev_Tout);
+
+/* n_steps x (3 rk_stage + vertical_implicit_solve) on the set fields, in
+ * place, using two stage buffers inside the workspace. */
+sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
+
+/* host_mass[m * n_fields + f] = sum over member m's prisms of 1^T M T_f.
+ * Synchronises the stream. */
+sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
+
+/* Wait for the context's stream and report any asynchronous HIP error. */
+sdg_status sdg_sync(sdg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLIMDG_H */

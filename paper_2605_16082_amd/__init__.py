@@ -1,0 +1,18 @@
+"""MI355X (gfx950) HIP implementation of the extruded-prism DG tracer step.
+
+The compute path is libslimdg.so (``csrc/``, C ABI in ``include/slimdg.h``);
+``slimdg`` is its ctypes binding.
+"""
+
+from .slimdg import (  # noqa: F401
+    SDG_FP32,
+    SDG_FP32_STATE_FP64_SOLVE,
+    SDG_FP64,
+    EXPORTED,
+    LIB_PATH,
+    Mesh,
+    SlimDG,
+    SlimDGError,
+    from_workload,
+    load_library,
+)

@@ -1,0 +1,589 @@
+// Host side of libslimdg: mesh validation and layout, workspace carving,
+// upload, parameter state and the extern "C" entry points of slimdg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "slimdg.h"
+
+using namespace sdg;
+
+namespace {
+
+thread_local std::string g_err;
+
+sdg_status fail(sdg_status st, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+sdg_status hip_fail(hipError_t e, const char* what) {
+  return fail(SDG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// Layout plan: cells, slots and workspace offsets.
+// ---------------------------------------------------------------------------
+struct Plan {
+  int C = 0, n_cells = 0, CS = 0, max_layers = 0, F = 0, prec = 0, n_members = 1;
+  bool fp32 = false;
+  int64_t n_prisms = 0, n_slots = 0, n_lslots = 0;
+  std::vector<int32_t> cell_base, cell_lbase, cell_depth, member_off;
+  std::vector<int64_t> zoff;  // per column: first row of its levels in desc.zlev
+  int n_tiles = 0;
+  // workspace offsets (bytes)
+  size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_col_member, o_member_off,
+      o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles, o_stage_a, o_stage_b, o_scratch, o_colmass,
+      o_msum, o_flag, total;
+  size_t state_bytes, velocity_bytes;
+};
+
+sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
+  if (!d) return fail(SDG_E_ARG, "mesh description is NULL");
+  if (d->n_tri < 1) return fail(SDG_E_MESH, "n_tri must be >= 1 (got %d)", d->n_tri);
+  if (d->n_vert < 3) return fail(SDG_E_MESH, "n_vert must be >= 3 (got %d)", d->n_vert);
+  if (!d->vxy || !d->tri || !d->nbr || !d->nlayers || !d->zlev)
+    return fail(SDG_E_ARG, "mesh arrays vxy, tri, nbr, nlayers and zlev must be non-NULL");
+  if (d->n_fields < 1 || d->n_fields > SDG_MAX_FIELDS)
+    return fail(SDG_E_UNSUPPORTED, "n_fields must be in 1..%d (got %d)", SDG_MAX_FIELDS, d->n_fields);
+  if (d->precision < SDG_FP64 || d->precision > SDG_FP32_STATE_FP64_SOLVE)
+    return fail(SDG_E_ARG, "unknown precision %d", d->precision);
+  const int C = d->n_tri;
+  P.C = C;
+  P.F = d->n_fields;
+  P.prec = d->precision;
+  P.fp32 = d->precision != SDG_FP64;
+  P.n_members = d->n_members < 1 ? 1 : d->n_members;
+  P.member_off.assign(P.n_members + 1, 0);
+  if (d->member_tri_off) {
+    if (d->n_members < 1) return fail(SDG_E_MESH, "n_members must be >= 1 with member_tri_off");
+    for (int m = 0; m <= P.n_members; ++m) P.member_off[m] = d->member_tri_off[m];
+    if (P.member_off[0] != 0 || P.member_off[P.n_members] != C)
+      return fail(SDG_E_MESH, "member_tri_off must start at 0 and end at n_tri");
+    for (int m = 0; m < P.n_members; ++m)
+      if (P.member_off[m + 1] <= P.member_off[m])
+        return fail(SDG_E_MESH, "member %d has no columns", m);
+  } else {
+    if (P.n_members != 1) return fail(SDG_E_MESH, "n_members > 1 needs member_tri_off");
+    P.member_off[1] = C;
+  }
+  std::vector<int32_t> col_member(C);
+  for (int m = 0; m < P.n_members; ++m)
+    for (int c = P.member_off[m]; c < P.member_off[m + 1]; ++c) col_member[c] = m;
+
+  // layers and level offsets
+  P.zoff.assign(C + 1, 0);
+  P.n_prisms = 0;
+  P.max_layers = 0;
+  for (int c = 0; c < C; ++c) {
+    const int n = d->nlayers[c];
+    if (n < 1 || n > 65535) return fail(SDG_E_MESH, "column %d has %d layers (need 1..65535)", c, n);
+    P.zoff[c + 1] = P.zoff[c] + (n + 1);
+    P.n_prisms += n;
+    P.max_layers = std::max(P.max_layers, n);
+  }
+  // triangles: vertex ids, orientation, level ordering
+  for (int c = 0; c < C; ++c) {
+    const int32_t* t = d->tri + 3 * c;
+    for (int k = 0; k < 3; ++k)
+      if (t[k] < 0 || t[k] >= d->n_vert) return fail(SDG_E_MESH, "triangle %d has vertex id %d out of range", c, t[k]);
+    const double* a = d->vxy + 2 * t[0];
+    const double* b = d->vxy + 2 * t[1];
+    const double* e = d->vxy + 2 * t[2];
+    const double jh = (b[0] - a[0]) * (e[1] - a[1]) - (e[0] - a[0]) * (b[1] - a[1]);
+    if (!(jh > 0.0)) return fail(SDG_E_MESH, "triangle %d is not counter-clockwise (J_h = %g)", c, jh);
+    const double* z = d->zlev + 3 * P.zoff[c];
+    for (int l = 0; l < d->nlayers[c]; ++l)
+      for (int v = 0; v < 3; ++v)
+        if (!(z[3 * l + v] > z[3 * (l + 1) + v]))
+          return fail(SDG_E_MESH, "column %d layer %d vertex %d has non-positive thickness", c, l, v);
+  }
+  // neighbours: symmetric, reversed shared edge, same member, conforming levels
+  for (int c = 0; c < C; ++c) {
+    for (int k = 0; k < 3; ++k) {
+      const int c2 = d->nbr[3 * c + k];
+      if (c2 == -1) continue;
+      if (c2 < 0 || c2 >= C || c2 == c) return fail(SDG_E_MESH, "column %d edge %d has invalid neighbour %d", c, k, c2);
+      if (col_member[c2] != col_member[c]) return fail(SDG_E_MESH, "column %d neighbours column %d of another member", c, c2);
+      const int va = d->tri[3 * c + k], vb = d->tri[3 * c + (k + 1) % 3];
+      int k2 = -1;
+      for (int j = 0; j < 3; ++j)
+        if (d->tri[3 * c2 + j] == vb && d->tri[3 * c2 + (j + 1) % 3] == va) k2 = j;
+      if (k2 < 0) return fail(SDG_E_MESH, "columns %d and %d do not share edge %d in opposite directions", c, c2, k);
+      if (d->nbr[3 * c2 + k2] != c) return fail(SDG_E_MESH, "neighbour relation %d -> %d is not symmetric", c, c2);
+      const int nl = std::min(d->nlayers[c], d->nlayers[c2]);
+      const double* z1 = d->zlev + 3 * P.zoff[c];
+      const double* z2 = d->zlev + 3 * P.zoff[c2];
+      const int a1 = k, b1 = (k + 1) % 3, a2 = (k2 + 1) % 3, b2 = k2;
+      for (int lv = 0; lv <= nl; ++lv)
+        if (z1[3 * lv + a1] != z2[3 * lv + a2] || z1[3 * lv + b1] != z2[3 * lv + b2])
+          return fail(SDG_E_MESH, "levels of columns %d and %d differ on their shared edge (level %d)", c, c2, lv);
+    }
+  }
+  // cells
+  P.n_cells = (C + kCell - 1) / kCell;
+  P.CS = P.n_cells * kCell;
+  P.cell_base.assign(P.n_cells + 1, 0);
+  P.cell_lbase.assign(P.n_cells + 1, 0);
+  P.cell_depth.assign(P.n_cells, 0);
+  int64_t sb = 0, lb = 0;
+  P.n_tiles = 0;
+  for (int k = 0; k < P.n_cells; ++k) {
+    int depth = 0;
+    for (int c = k * kCell; c < std::min(C, (k + 1) * kCell); ++c) depth = std::max(depth, (int)d->nlayers[c]);
+    P.cell_depth[k] = depth;
+    P.cell_base[k] = (int32_t)sb;
+    P.cell_lbase[k] = (int32_t)lb;
+    sb += (int64_t)depth * kCell;
+    lb += (int64_t)(depth + 1) * kCell;
+    P.n_tiles += (depth + kTileLayers - 1) / kTileLayers;
+    if (sb > INT32_MAX / 2 || lb > INT32_MAX / 2) return fail(SDG_E_UNSUPPORTED, "mesh too large for 32-bit slot indices");
+  }
+  P.cell_base[P.n_cells] = (int32_t)sb;
+  P.cell_lbase[P.n_cells] = (int32_t)lb;
+  P.n_slots = sb;
+  P.n_lslots = lb;
+
+  // workspace
+  const size_t es = P.fp32 ? 4 : 8;
+  P.state_bytes = (size_t)P.F * 6 * (size_t)P.n_slots * es;
+  P.velocity_bytes = (size_t)3 * 6 * (size_t)P.n_slots * es;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  P.o_cell_base = take(sizeof(int32_t) * (P.n_cells + 1));
+  P.o_cell_lbase = take(sizeof(int32_t) * (P.n_cells + 1));
+  P.o_nlay = take(sizeof(int32_t) * P.CS);
+  P.o_nbr_slot = take(sizeof(int32_t) * 3 * P.CS);
+  P.o_nbr_meta = take(sizeof(int32_t) * 3 * P.CS);
+  P.o_col_member = take(sizeof(int32_t) * P.CS);
+  P.o_member_off = take(sizeof(int32_t) * (P.n_members + 1));
+  P.o_geo = take(sizeof(double) * kGeoRows * P.CS);
+  P.o_geo32 = take(sizeof(float) * kGeoRows * P.CS);
+  P.o_xy = take(sizeof(double) * 6 * P.CS);
+  P.o_zl = take(sizeof(double) * 3 * (size_t)P.n_lslots);
+  P.o_zl32 = take(sizeof(float) * 3 * (size_t)P.n_lslots);
+  P.o_tiles = take(sizeof(WgTile) * std::max(P.n_tiles, 1));
+  P.o_stage_a = take(P.state_bytes);
+  P.o_stage_b = take(P.state_bytes);
+  P.o_scratch = take(sizeof(double) * (size_t)(18 + 6 * P.F) * (size_t)P.n_slots);
+  P.o_colmass = take(sizeof(double) * (size_t)P.F * P.CS);
+  P.o_msum = take(sizeof(double) * (size_t)P.F * P.n_members);
+  P.o_flag = take(sizeof(int32_t) * 64);
+  P.total = o;
+  return SDG_OK;
+}
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+
+ private:
+  int prev_ = -1;
+};
+
+}  // namespace
+
+struct sdg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool have_mesh = false;
+  Plan plan;
+  DevMesh dm{};
+  char* ws = nullptr;
+  WgTile* tiles = nullptr;
+  int32_t* member_off_dev = nullptr;
+  double* colmass = nullptr;
+  double* msum = nullptr;
+  int32_t* flag = nullptr;
+  void* stage_a = nullptr;
+  void* stage_b = nullptr;
+  double* scratch = nullptr;
+  // state set by the caller
+  bool have_params = false;
+  double dt = 0.0, eta = 4.0;
+  double t_ext[kMaxFields] = {0, 0, 0, 0};
+  bool w_zero = false, check_finite = false;
+  const void* U = nullptr;
+  const double* kappa = nullptr;
+  void* state = nullptr;
+};
+
+extern "C" {
+
+int sdg_abi_version(void) { return SDG_ABI_VERSION; }
+
+const char* sdg_last_error(void) { return g_err.c_str(); }
+
+sdg_status sdg_query_layout(const sdg_mesh_desc* mesh, sdg_layout* out) {
+  if (!out) return fail(SDG_E_ARG, "output layout is NULL");
+  Plan P;
+  sdg_status st = plan_mesh(mesh, P);
+  if (st != SDG_OK) return st;
+  out->n_prisms = P.n_prisms;
+  out->n_slots = P.n_slots;
+  out->n_cells = P.n_cells;
+  out->max_layers = P.max_layers;
+  out->n_fields = P.F;
+  out->state_elem_bytes = P.fp32 ? 4 : 8;
+  out->state_bytes = P.state_bytes;
+  out->velocity_bytes = P.velocity_bytes;
+  out->workspace_bytes = P.total;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_prism_slots(const sdg_mesh_desc* mesh, int64_t* host_slots) {
+  if (!host_slots) return fail(SDG_E_ARG, "host_slots is NULL");
+  Plan P;
+  sdg_status st = plan_mesh(mesh, P);
+  if (st != SDG_OK) return st;
+  int64_t q = 0;
+  for (int c = 0; c < P.C; ++c) {
+    const int k = c / kCell, lane = c % kCell;
+    for (int l = 0; l < mesh->nlayers[c]; ++l) host_slots[q++] = (int64_t)P.cell_base[k] + (int64_t)l * kCell + lane;
+  }
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_create(sdg_ctx** out, int device, void* hip_stream) {
+  if (!out) return fail(SDG_E_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(SDG_E_ARG, "device %d out of range (%d devices)", device, n);
+  sdg_ctx* c = new (std::nothrow) sdg_ctx();
+  if (!c) return fail(SDG_E_ARG, "out of host memory");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *out = c;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_destroy(sdg_ctx* ctx) {
+  delete ctx;
+  return SDG_OK;
+}
+
+sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_workspace, size_t ws_bytes) {
+  if (!ctx) return fail(SDG_E_ARG, "context is NULL");
+  ctx->have_mesh = false;
+  ctx->U = nullptr;
+  ctx->kappa = nullptr;
+  ctx->state = nullptr;
+  Plan P;
+  sdg_status st = plan_mesh(mesh, P);
+  if (st != SDG_OK) return st;
+  if (!dev_workspace) return fail(SDG_E_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) & 255) return fail(SDG_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < P.total)
+    return fail(SDG_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, P.total);
+  DeviceGuard g(ctx->device);
+  const int CS = P.CS, C = P.C;
+  // host images of the device tables
+  std::vector<int32_t> nlay(CS, 0), nbr_slot(3 * (size_t)CS, -1), nbr_meta(3 * (size_t)CS, 0), colmem(CS, -1);
+  std::vector<double> xy(6 * (size_t)CS, 0.0), zl(3 * (size_t)P.n_lslots, 0.0);
+  std::vector<WgTile> tiles;
+  tiles.reserve(P.n_tiles);
+  for (int k = 0; k < P.n_cells; ++k)
+    for (int l0 = 0; l0 < P.cell_depth[k]; l0 += kTileLayers) tiles.push_back({k, l0});
+  for (int m = 0; m < P.n_members; ++m)
+    for (int c = P.member_off[m]; c < P.member_off[m + 1]; ++c) colmem[c] = m;
+  for (int c = 0; c < C; ++c) {
+    const int k = c / kCell, lane = c % kCell;
+    const int n = mesh->nlayers[c];
+    nlay[c] = n;
+    for (int v = 0; v < 3; ++v) {
+      const int vid = mesh->tri[3 * c + v];
+      xy[(2 * v) * (size_t)CS + c] = mesh->vxy[2 * vid];
+      xy[(2 * v + 1) * (size_t)CS + c] = mesh->vxy[2 * vid + 1];
+    }
+    for (int e = 0; e < 3; ++e) {
+      const int c2 = mesh->nbr[3 * c + e];
+      if (c2 < 0) continue;
+      const int va = mesh->tri[3 * c + e], vb = mesh->tri[3 * c + (e + 1) % 3];
+      int k2 = 0;
+      for (int j = 0; j < 3; ++j)
+        if (mesh->tri[3 * c2 + j] == vb && mesh->tri[3 * c2 + (j + 1) % 3] == va) k2 = j;
+      nbr_slot[e * (size_t)CS + c] = P.cell_base[c2 / kCell] + c2 % kCell;
+      nbr_meta[e * (size_t)CS + c] = (mesh->nlayers[c2] << 2) | k2;
+    }
+    const double* z = mesh->zlev + 3 * P.zoff[c];
+    for (int lv = 0; lv <= n; ++lv)
+      for (int v = 0; v < 3; ++v)
+        zl[v * (size_t)P.n_lslots + P.cell_lbase[k] + (size_t)lv * kCell + lane] = z[3 * lv + v];
+  }
+  char* ws = static_cast<char*>(dev_workspace);
+  hipStream_t s = ctx->stream;
+  struct Cp { size_t off; const void* src; size_t bytes; };
+  const Cp cps[] = {
+      {P.o_cell_base, P.cell_base.data(), sizeof(int32_t) * P.cell_base.size()},
+      {P.o_cell_lbase, P.cell_lbase.data(), sizeof(int32_t) * P.cell_lbase.size()},
+      {P.o_nlay, nlay.data(), sizeof(int32_t) * nlay.size()},
+      {P.o_nbr_slot, nbr_slot.data(), sizeof(int32_t) * nbr_slot.size()},
+      {P.o_nbr_meta, nbr_meta.data(), sizeof(int32_t) * nbr_meta.size()},
+      {P.o_col_member, colmem.data(), sizeof(int32_t) * colmem.size()},
+      {P.o_member_off, P.member_off.data(), sizeof(int32_t) * P.member_off.size()},
+      {P.o_xy, xy.data(), sizeof(double) * xy.size()},
+      {P.o_zl, zl.data(), sizeof(double) * zl.size()},
+      {P.o_tiles, tiles.data(), sizeof(WgTile) * tiles.size()},
+  };
+  for (const Cp& cp : cps) {
+    if (cp.bytes == 0) continue;
+    hipError_t e = hipMemcpyAsync(ws + cp.off, cp.src, cp.bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync (mesh upload)");
+  }
+  DevMesh& dm = ctx->dm;
+  dm.n_cols = C;
+  dm.n_cells = P.n_cells;
+  dm.n_col_slots = CS;
+  dm.max_layers = P.max_layers;
+  dm.n_slots = P.n_slots;
+  dm.n_lslots = P.n_lslots;
+  dm.cell_base = reinterpret_cast<const int32_t*>(ws + P.o_cell_base);
+  dm.cell_lbase = reinterpret_cast<const int32_t*>(ws + P.o_cell_lbase);
+  dm.nlay = reinterpret_cast<const int32_t*>(ws + P.o_nlay);
+  dm.nbr_slot = reinterpret_cast<const int32_t*>(ws + P.o_nbr_slot);
+  dm.nbr_meta = reinterpret_cast<const int32_t*>(ws + P.o_nbr_meta);
+  dm.geo = reinterpret_cast<const double*>(ws + P.o_geo);
+  dm.geo32 = reinterpret_cast<const float*>(ws + P.o_geo32);
+  dm.zl = reinterpret_cast<const double*>(ws + P.o_zl);
+  dm.zl32 = reinterpret_cast<const float*>(ws + P.o_zl32);
+  dm.xy = reinterpret_cast<const double*>(ws + P.o_xy);
+  dm.col_member = reinterpret_cast<const int32_t*>(ws + P.o_col_member);
+  hipError_t e = launch_geometry(dm, reinterpret_cast<double*>(ws + P.o_geo), reinterpret_cast<float*>(ws + P.o_geo32), s);
+  if (e != hipSuccess) return hip_fail(e, "geometry kernel launch");
+  e = launch_z32(dm, reinterpret_cast<float*>(ws + P.o_zl32), s);
+  if (e != hipSuccess) return hip_fail(e, "level conversion launch");
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "mesh upload");
+  ctx->plan = std::move(P);
+  const Plan& Q = ctx->plan;
+  ctx->ws = ws;
+  ctx->tiles = reinterpret_cast<WgTile*>(ws + Q.o_tiles);
+  ctx->member_off_dev = reinterpret_cast<int32_t*>(ws + Q.o_member_off);
+  ctx->colmass = reinterpret_cast<double*>(ws + Q.o_colmass);
+  ctx->msum = reinterpret_cast<double*>(ws + Q.o_msum);
+  ctx->flag = reinterpret_cast<int32_t*>(ws + Q.o_flag);
+  ctx->stage_a = ws + Q.o_stage_a;
+  ctx->stage_b = ws + Q.o_stage_b;
+  ctx->scratch = reinterpret_cast<double*>(ws + Q.o_scratch);
+  ctx->have_mesh = true;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
+  if (!ctx || !p) return fail(SDG_E_ARG, "context or params is NULL");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_params needs an uploaded mesh");
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(SDG_E_ARG, "dt must be finite and > 0 (got %g)", p->dt);
+  const double eta = p->penalty_eta > 0.0 ? p->penalty_eta : 4.0;
+  if (!std::isfinite(eta)) return fail(SDG_E_ARG, "penalty_eta must be finite");
+  for (int f = 0; f < ctx->plan.F; ++f) {
+    const double v = p->t_ext ? p->t_ext[f] : 0.0;
+    if (!std::isfinite(v)) return fail(SDG_E_ARG, "t_ext[%d] is not finite", f);
+    ctx->t_ext[f] = v;
+  }
+  ctx->dt = p->dt;
+  ctx->eta = eta;
+  ctx->w_zero = p->w_is_zero != 0;
+  ctx->check_finite = p->check_finite != 0;
+  ctx->have_params = true;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_set_velocity(sdg_ctx* ctx, const void* dev_uvw) {
+  if (!ctx || !dev_uvw) return fail(SDG_E_ARG, "context or velocity is NULL");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_velocity needs an uploaded mesh");
+  ctx->U = dev_uvw;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_set_diffusivity(sdg_ctx* ctx, const double* dev_kappa) {
+  if (!ctx || !dev_kappa) return fail(SDG_E_ARG, "context or diffusivity is NULL");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_diffusivity needs an uploaded mesh");
+  ctx->kappa = dev_kappa;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_set_fields(sdg_ctx* ctx, void* dev_state) {
+  if (!ctx || !dev_state) return fail(SDG_E_ARG, "context or state is NULL");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_fields needs an uploaded mesh");
+  ctx->state = dev_state;
+  g_err.clear();
+  return SDG_OK;
+}
+
+namespace {
+
+sdg_status check_explicit(sdg_ctx* ctx, const char* who) {
+  if (!ctx) return fail(SDG_E_ARG, "%s: context is NULL", who);
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "%s needs an uploaded mesh", who);
+  if (!ctx->have_params) return fail(SDG_E_STATE, "%s needs sdg_set_params", who);
+  if (!ctx->U) return fail(SDG_E_STATE, "%s needs sdg_set_velocity", who);
+  return SDG_OK;
+}
+
+StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, double a, double b) {
+  StageArgs s{};
+  s.m = ctx->dm;
+  s.tiles = ctx->tiles;
+  s.n_tiles = ctx->plan.n_tiles;
+  s.n_fields = ctx->plan.F;
+  s.Tn = Tn;
+  s.Ts = Ts;
+  s.Tout = Tout;
+  s.U = ctx->U;
+  for (int f = 0; f < kMaxFields; ++f) s.t_ext[f] = ctx->t_ext[f];
+  s.dt = ctx->dt;
+  s.a = a;
+  s.b = b;
+  return s;
+}
+
+constexpr double kRk[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
+
+sdg_status enqueue_stage(sdg_ctx* ctx, int stage, const void* Tn, const void* Ts, void* Tout) {
+  StageArgs s = stage_args(ctx, Tn, Ts, Tout, kRk[stage][0], kRk[stage][1]);
+  hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, false, stage > 0, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "rk_stage launch");
+  return SDG_OK;
+}
+
+sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout) {
+  SolveArgs a{};
+  a.m = ctx->dm;
+  a.n_fields = ctx->plan.F;
+  a.Tstar = Tstar;
+  a.Tout = Tout;
+  a.kappa = ctx->kappa;
+  a.scratch = ctx->scratch;
+  a.dt = ctx->dt;
+  a.eta = ctx->eta;
+  hipError_t e = launch_vsolve(a, ctx->plan.fp32, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "vertical solve launch");
+  return SDG_OK;
+}
+
+}  // namespace
+
+sdg_status sdg_rhs_3d(sdg_ctx* ctx, const void* dev_T, void* dev_L) {
+  sdg_status st = check_explicit(ctx, "sdg_rhs_3d");
+  if (st != SDG_OK) return st;
+  if (!dev_T || !dev_L) return fail(SDG_E_ARG, "sdg_rhs_3d: NULL buffer");
+  if (dev_T == dev_L) return fail(SDG_E_ARG, "sdg_rhs_3d: output must not alias input");
+  DeviceGuard g(ctx->device);
+  StageArgs s = stage_args(ctx, nullptr, dev_T, dev_L, 0.0, 1.0);
+  hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, true, false, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "rhs_3d launch");
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_rk_stage(sdg_ctx* ctx, int stage, const void* dev_Tn, const void* dev_Ts, void* dev_Tout) {
+  sdg_status st = check_explicit(ctx, "sdg_rk_stage");
+  if (st != SDG_OK) return st;
+  if (stage < 0 || stage > 2) return fail(SDG_E_ARG, "sdg_rk_stage: stage must be 0, 1 or 2 (got %d)", stage);
+  if (!dev_Ts || !dev_Tout || (stage > 0 && !dev_Tn)) return fail(SDG_E_ARG, "sdg_rk_stage: NULL buffer");
+  if (dev_Tout == dev_Ts || (stage > 0 && dev_Tout == dev_Tn))
+    return fail(SDG_E_ARG, "sdg_rk_stage: output must not alias an input");
+  DeviceGuard g(ctx->device);
+  st = enqueue_stage(ctx, stage, dev_Tn, dev_Ts, dev_Tout);
+  if (st == SDG_OK) g_err.clear();
+  return st;
+}
+
+sdg_status sdg_vertical_implicit_solve(sdg_ctx* ctx, const void* dev_Tstar, void* dev_Tout) {
+  if (!ctx) return fail(SDG_E_ARG, "context is NULL");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_vertical_implicit_solve needs an uploaded mesh");
+  if (!ctx->have_params) return fail(SDG_E_STATE, "sdg_vertical_implicit_solve needs sdg_set_params");
+  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_vertical_implicit_solve needs sdg_set_diffusivity");
+  if (!dev_Tstar || !dev_Tout) return fail(SDG_E_ARG, "sdg_vertical_implicit_solve: NULL buffer");
+  DeviceGuard g(ctx->device);
+  sdg_status st = enqueue_solve(ctx, dev_Tstar, dev_Tout);
+  if (st == SDG_OK) g_err.clear();
+  return st;
+}
+
+sdg_status sdg_step(sdg_ctx* ctx, int n_steps) {
+  sdg_status st = check_explicit(ctx, "sdg_step");
+  if (st != SDG_OK) return st;
+  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step needs sdg_set_diffusivity");
+  if (!ctx->state) return fail(SDG_E_STATE, "sdg_step needs sdg_set_fields");
+  if (n_steps < 0) return fail(SDG_E_ARG, "n_steps must be >= 0");
+  DeviceGuard g(ctx->device);
+  void* X = ctx->state;
+  void* A = ctx->stage_a;
+  void* B = ctx->stage_b;
+  for (int n = 0; n < n_steps; ++n) {
+    if ((st = enqueue_stage(ctx, 0, nullptr, X, A)) != SDG_OK) return st;
+    if ((st = enqueue_stage(ctx, 1, X, A, B)) != SDG_OK) return st;
+    if ((st = enqueue_stage(ctx, 2, X, B, A)) != SDG_OK) return st;
+    if ((st = enqueue_solve(ctx, A, X)) != SDG_OK) return st;
+  }
+  if (ctx->check_finite && n_steps > 0) {
+    hipError_t e = launch_finite_check(ctx->dm, X, ctx->plan.F, ctx->plan.fp32, ctx->flag, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "finite check launch");
+    int32_t h = 0;
+    e = hipMemcpyAsync(&h, ctx->flag, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "finite check");
+    if (h) return fail(SDG_E_NUMERIC, "non-finite values in the state after %d steps", n_steps);
+  }
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass) {
+  if (!ctx || !dev_T || !host_mass) return fail(SDG_E_ARG, "sdg_mass: NULL argument");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_mass needs an uploaded mesh");
+  DeviceGuard g(ctx->device);
+  const Plan& P = ctx->plan;
+  hipError_t e = launch_column_mass(ctx->dm, dev_T, P.F, P.fp32, ctx->colmass, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "column mass launch");
+  e = launch_member_sum(ctx->colmass, P.CS, P.F, ctx->member_off_dev, P.n_members, ctx->msum, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "member sum launch");
+  e = hipMemcpyAsync(host_mass, ctx->msum, sizeof(double) * P.F * P.n_members, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "sdg_mass");
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_sync(sdg_ctx* ctx) {
+  if (!ctx) return fail(SDG_E_ARG, "context is NULL");
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "sdg_sync");
+  g_err.clear();
+  return SDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal definitions shared by the host code and the kernels of libslimdg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace sdg {
+
+constexpr int kCell = 64;           // columns per cell = wavefront width
+constexpr int kMaxFields = 4;
+
+// Per-column geometry rows in DevMesh::geo ([kGeoRows][n_col_slots]).
+enum GeoRow : int {
+  G_XXI = 0,  // x1 - x0
+  G_XET = 1,  // x2 - x0
+  G_YXI = 2,  // y1 - y0
+  G_YET = 3,  // y2 - y0
+  G_JH = 4,   // (x1-x0)(y2-y0) - (x2-x0)(y1-y0) = 2 * area
+  G_NX = 5,   // 5,6,7: outward unit normal x of edge k
+  G_NY = 8,   // 8,9,10
+  G_LE = 11,  // 11,12,13: edge length
+  kGeoRows = 14
+};
+
+// Device view of an uploaded mesh.  Column slot = cell * 64 + lane; prism
+// slot = cell_base[cell] + layer * 64 + lane; level slot = cell_lbase[cell]
+// + level * 64 + lane.
+struct DevMesh {
+  int32_t n_cols;          // live columns
+  int32_t n_cells;
+  int32_t n_col_slots;     // n_cells * 64
+  int32_t max_layers;
+  int64_t n_slots;         // prism slots
+  int64_t n_lslots;        // level slots
+  const int32_t* cell_base;    // [n_cells + 1]
+  const int32_t* cell_lbase;   // [n_cells + 1]
+  const int32_t* nlay;         // [n_col_slots], 0 on padding columns
+  const int32_t* nbr_slot;     // [3][n_col_slots]: prism slot of the neighbour's layer 0, or -1
+  const int32_t* nbr_meta;     // [3][n_col_slots]: (neighbour nlayers << 2) | neighbour edge
+  const double* geo;           // [kGeoRows][n_col_slots]
+  const float* geo32;          // same, float
+  const double* zl;            // [3][n_lslots] level heights
+  const float* zl32;           // same, float
+  const double* xy;            // [6][n_col_slots] x0,y0,x1,y1,x2,y2 (input of the geometry kernel)
+  const int32_t* col_member;   // [n_col_slots] member id (-1 on padding)
+};
+
+// A workgroup of the per-prism kernels covers 4 consecutive layers of one
+// cell: (cell, first layer).
+struct WgTile {
+  int32_t cell;
+  int32_t layer0;
+};
+constexpr int kTileLayers = 4;
+
+struct StageArgs {
+  DevMesh m;
+  const WgTile* tiles;
+  int32_t n_tiles;
+  int32_t n_fields;
+  const void* Tn;      // [F][6][n_slots]
+  const void* Ts;
+  void* Tout;
+  const void* U;       // [3][6][n_slots]
+  double t_ext[kMaxFields];
+  double dt;
+  double a, b;         // Tout = a Tn + b (Ts + dt L)
+};
+
+struct SolveArgs {
+  DevMesh m;
+  int32_t n_fields;
+  const void* Tstar;
+  void* Tout;
+  const double* kappa;   // [max_layers]
+  double* scratch;       // [18 + 6F][n_slots] doubles
+  double dt;
+  double eta;
+};
+
+// Kernel launchers (defined next to their kernels).
+hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStream_t s);
+hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
+hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,
+                        bool read_tn, hipStream_t s);
+hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, hipStream_t s);
+hipError_t launch_column_mass(const DevMesh& m, const void* T, int n_fields, bool fp32,
+                              double* col_mass, hipStream_t s);
+hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fields,
+                             const int32_t* member_off, int n_members, double* out,
+                             hipStream_t s);
+hipError_t launch_finite_check(const DevMesh& m, const void* T, int n_fields, bool fp32,
+                               int32_t* flag, hipStream_t s);
+
+// Workgroup index -> tile index so that each of the 8 XCDs (which receive
+// workgroups round-robin) processes one contiguous range of tiles, keeping
+// lateral neighbours in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int q = n >> 3, r = n & 7;
+  const int x = b & 7, j = b >> 3;
+  return (x < r) ? x * (q + 1) + j : r * (q + 1) + (x - r) * q + j;
+}
+
+}  // namespace sdg

@@ -1,0 +1,391 @@
+// Explicit DG operator and SSP-RK3 stage on extruded linear prisms.
+//
+// One thread per prism.  A workgroup of 256 threads covers 4 consecutive
+// layers of one cell of 64 columns, so each wavefront reads 64 consecutive
+// slots of every nodal array (cell layout, section 2.1.1 of the paper, with
+// wavefront-sized cells).  Per prism and field it computes
+//
+//   R_i = int_K T U.grad(phi_i) dV - sum_faces int_f phi_i Fhat dS
+//   L   = M^-1 R                          (block-diagonal mass matrix)
+//   out = a Tn + b (Ts + dt L)            (SSP-RK3, Shu-Osher form)
+//
+// with the quadrature that defines the operator: 6-point degree-4 triangle
+// rule x 2-point Gauss in zeta for the volume and horizontal faces, 3-point
+// Gauss along edges x 2-point in zeta for lateral faces; upwind flux per
+// quadrature point, Fhat dS = max(u_n dS, 0) T_in + min(u_n dS, 0) T_out
+// with u_n the average of the two velocity traces.
+//
+// The volume term uses contravariant fluxes: with alpha = y_eta u - x_eta v
+// and beta = x_xi v - y_xi u, the integrand T U.(|J| grad phi_i) equals
+// T (dphi_i/dxi z_zeta alpha + dphi_i/deta z_zeta beta
+//    + dphi_i/dzeta (J_h w - z_xi alpha - z_eta beta)),
+// so the geometric work is shared by all fields.  The mass matrix of a prism
+// is H (x) Mz with H = [2 1; 1 2]/3 and Mz_ab = J_h int lambda_a lambda_b
+// z_zeta, so M^-1 = [2 -1; -1 2] (x) Mz^-1 and only a symmetric 3x3 inverse
+// is needed.
+#include "internal.h"
+
+namespace sdg {
+namespace {
+
+// 6-point triangle rule: barycentric points (lambda0, lambda1, lambda2);
+// weights include the reference-triangle area 1/2.
+constexpr double kA1 = 0.44594849091596488631832925388305199;
+constexpr double kB1 = 0.10810301816807022736334149223390401;
+constexpr double kW1 = 0.5 * 0.22338158967801146569500700843312280;
+constexpr double kA2 = 0.091576213509770743459571463402201508;
+constexpr double kB2 = 0.81684757298045851308085707319559698;
+constexpr double kW2 = 0.5 * 0.10995174365532186763832632490021053;
+constexpr double kL0[6] = {kB1, kA1, kA1, kB2, kA2, kA2};
+constexpr double kL1[6] = {kA1, kA1, kB1, kA2, kA2, kB2};
+constexpr double kL2[6] = {kA1, kB1, kA1, kA2, kB2, kA2};
+constexpr double kTw[6] = {kW1, kW1, kW1, kW2, kW2, kW2};
+// zeta = -1/sqrt(3), +1/sqrt(3): t = (1+zeta)/2, b = (1-zeta)/2; weights 1.
+constexpr double kZt[2] = {0.21132486540518711774542560974902127, 0.78867513459481288225457439025097873};
+constexpr double kZb[2] = {0.78867513459481288225457439025097873, 0.21132486540518711774542560974902127};
+// 3-point Gauss on [0, 1].
+constexpr double kS[3] = {0.11270166537925831148207346002176005, 0.5, 0.88729833462074168851792653997823995};
+constexpr double kSw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+template <typename R> __device__ __forceinline__ const R* geo_of(const DevMesh& m);
+template <> __device__ __forceinline__ const double* geo_of<double>(const DevMesh& m) { return m.geo; }
+template <> __device__ __forceinline__ const float* geo_of<float>(const DevMesh& m) { return m.geo32; }
+template <typename R> __device__ __forceinline__ const R* zl_of(const DevMesh& m);
+template <> __device__ __forceinline__ const double* zl_of<double>(const DevMesh& m) { return m.zl; }
+template <> __device__ __forceinline__ const float* zl_of<float>(const DevMesh& m) { return m.zl32; }
+
+template <typename R>
+__device__ __forceinline__ R upos(R x) { return x > R(0) ? x : R(0); }
+template <typename R>
+__device__ __forceinline__ R uneg(R x) { return x < R(0) ? x : R(0); }
+
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+  const DevMesh& m = a.m;
+  const WgTile tile = a.tiles[xcd_tile(blockIdx.x, a.n_tiles)];
+  const int lane = threadIdx.x & (kCell - 1);
+  const int l = tile.layer0 + (threadIdx.x >> 6);
+  const int c = tile.cell * kCell + lane;
+  const int N = m.nlay[c];
+  if (l >= N) return;
+
+  const size_t S = (size_t)m.n_slots;
+  const size_t LS = (size_t)m.n_lslots;
+  const int CS = m.n_col_slots;
+  const size_t p = (size_t)m.cell_base[tile.cell] + (size_t)l * kCell + lane;
+  const size_t lt = (size_t)m.cell_lbase[tile.cell] + (size_t)l * kCell + lane;
+  const R* __restrict__ Ts = static_cast<const R*>(a.Ts);
+  const R* __restrict__ U = static_cast<const R*>(a.U);
+  const R* __restrict__ geo = geo_of<R>(m);
+  const R* __restrict__ zl = zl_of<R>(m);
+
+  const R xxi = geo[G_XXI * CS + c], xet = geo[G_XET * CS + c];
+  const R yxi = geo[G_YXI * CS + c], yet = geo[G_YET * CS + c];
+  const R Jh = geo[G_JH * CS + c];
+
+  R zt[3], zb[3], dz[3];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    zt[v] = zl[v * LS + lt];
+    zb[v] = zl[v * LS + lt + kCell];
+    dz[v] = zt[v] - zb[v];
+  }
+
+  R T[NF][6];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) T[f][i] = Ts[(size_t)(f * 6 + i) * S + p];
+  R u[6], v[6], w[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    u[i] = U[(size_t)(0 * 6 + i) * S + p];
+    v[i] = U[(size_t)(1 * 6 + i) * S + p];
+    w[i] = WZ ? R(0) : U[(size_t)(2 * 6 + i) * S + p];
+  }
+
+  R res[NF][6];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) res[f][i] = R(0);
+
+  // ---------------- volume term ----------------
+  {
+    R sx[NF][2], se[NF][2], sz[NF][3];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      sx[f][0] = sx[f][1] = se[f][0] = se[f][1] = R(0);
+      sz[f][0] = sz[f][1] = sz[f][2] = R(0);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const R tk = R(kZt[k]), bk = R(kZb[k]);
+      R ua[3], va[3], wa[3], ta[NF][3];
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        ua[n] = tk * u[n] + bk * u[n + 3];
+        va[n] = tk * v[n] + bk * v[n + 3];
+        wa[n] = WZ ? R(0) : tk * w[n] + bk * w[n + 3];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ta[f][n] = tk * T[f][n] + bk * T[f][n + 3];
+      }
+      const R z_xi = tk * (zt[1] - zt[0]) + bk * (zb[1] - zb[0]);
+      const R z_et = tk * (zt[2] - zt[0]) + bk * (zb[2] - zb[0]);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const R l0 = R(kL0[q]), l1 = R(kL1[q]), l2 = R(kL2[q]), wq = R(kTw[q]);
+        const R uq = l0 * ua[0] + l1 * ua[1] + l2 * ua[2];
+        const R vq = l0 * va[0] + l1 * va[1] + l2 * va[2];
+        const R zz = R(0.5) * (l0 * dz[0] + l1 * dz[1] + l2 * dz[2]);
+        const R al = yet * uq - xet * vq;
+        const R be = xxi * vq - yxi * uq;
+        const R Vx = wq * zz * al;
+        const R Ve = wq * zz * be;
+        R Vz = -(z_xi * al + z_et * be);
+        if (!WZ) Vz += Jh * (l0 * wa[0] + l1 * wa[1] + l2 * wa[2]);
+        Vz *= wq;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const R tq = l0 * ta[f][0] + l1 * ta[f][1] + l2 * ta[f][2];
+          sx[f][k] += tq * Vx;
+          se[f][k] += tq * Ve;
+          const R wz = tq * Vz;
+          sz[f][0] += l0 * wz;
+          sz[f][1] += l1 * wz;
+          sz[f][2] += l2 * wz;
+        }
+      }
+    }
+    // dphi/dxi = dlambda/dxi * (t or b), dphi/dzeta = +-lambda/2
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const R sxt = R(kZt[0]) * sx[f][0] + R(kZt[1]) * sx[f][1];
+      const R sxb = R(kZb[0]) * sx[f][0] + R(kZb[1]) * sx[f][1];
+      const R set = R(kZt[0]) * se[f][0] + R(kZt[1]) * se[f][1];
+      const R seb = R(kZb[0]) * se[f][0] + R(kZb[1]) * se[f][1];
+      res[f][0] = -sxt - set + R(0.5) * sz[f][0];
+      res[f][1] = sxt + R(0.5) * sz[f][1];
+      res[f][2] = set + R(0.5) * sz[f][2];
+      res[f][3] = -sxb - seb - R(0.5) * sz[f][0];
+      res[f][4] = sxb - R(0.5) * sz[f][1];
+      res[f][5] = seb - R(0.5) * sz[f][2];
+    }
+  }
+
+  // ---------------- lateral faces ----------------
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int A = e, B = (e + 1) % 3;
+    const int nslot = m.nbr_slot[e * CS + c];
+    const int meta = m.nbr_meta[e * CS + c];
+    const bool interior = nslot >= 0;
+    if (interior && l >= (meta >> 2)) continue;  // shallower neighbour: wall
+    const R nx = geo[(G_NX + e) * CS + c], ny = geo[(G_NY + e) * CS + c];
+    const R Le = geo[(G_LE + e) * CS + c];
+    // normal velocity at the 4 face nodes (A top, B top, A bottom, B bottom)
+    R un[4] = {nx * u[A] + ny * v[A], nx * u[B] + ny * v[B], nx * u[A + 3] + ny * v[A + 3],
+               nx * u[B + 3] + ny * v[B + 3]};
+    size_t pn = 0;
+    int nA = 0, nB = 0;
+    if (interior) {
+      const int kp = meta & 3;
+      nA = (kp + 1) % 3;  // neighbour's local vertex that is our vertex A
+      nB = kp;            // ... our vertex B
+      pn = (size_t)nslot + (size_t)l * kCell;
+      const int nodes[4] = {nA, nB, nA + 3, nB + 3};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const R uo = U[(size_t)(0 * 6 + nodes[j]) * S + pn];
+        const R vo = U[(size_t)(1 * 6 + nodes[j]) * S + pn];
+        un[j] = R(0.5) * (un[j] + nx * uo + ny * vo);
+      }
+    }
+    R up[3][2], um[3][2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const R s = R(kS[j]), s1 = R(1) - R(kS[j]);
+      const R dS = R(kSw[j]) * Le * R(0.5) * (s1 * dz[A] + s * dz[B]);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const R tk = R(kZt[k]), bk = R(kZb[k]);
+        const R q = (s1 * (tk * un[0] + bk * un[2]) + s * (tk * un[1] + bk * un[3])) * dS;
+        up[j][k] = upos(q);
+        um[j][k] = uneg(q);
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      R to[4];
+      if (interior) {
+        to[0] = Ts[(size_t)(f * 6 + nA) * S + pn];
+        to[1] = Ts[(size_t)(f * 6 + nB) * S + pn];
+        to[2] = Ts[(size_t)(f * 6 + nA + 3) * S + pn];
+        to[3] = Ts[(size_t)(f * 6 + nB + 3) * S + pn];
+      } else {
+        to[0] = to[1] = to[2] = to[3] = R(a.t_ext[f]);
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const R s = R(kS[j]), s1 = R(1) - R(kS[j]);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const R tk = R(kZt[k]), bk = R(kZb[k]);
+          const R ti = s1 * (tk * T[f][A] + bk * T[f][A + 3]) + s * (tk * T[f][B] + bk * T[f][B + 3]);
+          const R tq = s1 * (tk * to[0] + bk * to[2]) + s * (tk * to[1] + bk * to[3]);
+          const R fl = up[j][k] * ti + um[j][k] * tq;
+          res[f][A] -= s1 * tk * fl;
+          res[f][B] -= s * tk * fl;
+          res[f][A + 3] -= s1 * bk * fl;
+          res[f][B + 3] -= s * bk * fl;
+        }
+      }
+    }
+  }
+
+  // ---------------- top and bottom faces ----------------
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    // side 0: top face (nodes 0..2, neighbour above, its bottom nodes);
+    // side 1: bottom face (nodes 3..5, neighbour below, its top nodes).
+    const int o = side == 0 ? 0 : 3;
+    const int oo = side == 0 ? 3 : 0;
+    const bool has_nb = side == 0 ? (l > 0) : (l < N - 1);
+    const size_t pn = side == 0 ? p - kCell : p + kCell;
+    const R* zf = side == 0 ? zt : zb;
+    // J_h * grad_h z of the (planar) face
+    const R zxi = zf[1] - zf[0], zet = zf[2] - zf[0];
+    const R jzx = zxi * yet - zet * yxi;
+    const R jzy = zet * xxi - zxi * xet;
+    const R sg = side == 0 ? R(1) : R(-1);
+    R un[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      R val = -(u[o + n] * jzx + v[o + n] * jzy);
+      if (!WZ) val += Jh * w[o + n];
+      un[n] = val;
+    }
+    if (has_nb) {
+#pragma unroll
+      for (int n = 0; n < 3; ++n) {
+        const R uo = U[(size_t)(0 * 6 + oo + n) * S + pn];
+        const R vo = U[(size_t)(1 * 6 + oo + n) * S + pn];
+        R val = -(uo * jzx + vo * jzy);
+        if (!WZ) val += Jh * U[(size_t)(2 * 6 + oo + n) * S + pn];
+        un[n] = R(0.5) * (un[n] + val);
+      }
+    }
+    R up[6], um[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const R fq = sg * R(kTw[q]) * (R(kL0[q]) * un[0] + R(kL1[q]) * un[1] + R(kL2[q]) * un[2]);
+      up[q] = upos(fq);
+      um[q] = uneg(fq);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      R to[3];
+      if (has_nb) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n) to[n] = Ts[(size_t)(f * 6 + oo + n) * S + pn];
+      } else {
+        to[0] = to[1] = to[2] = R(a.t_ext[f]);
+      }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const R l0 = R(kL0[q]), l1 = R(kL1[q]), l2 = R(kL2[q]);
+        const R ti = l0 * T[f][o] + l1 * T[f][o + 1] + l2 * T[f][o + 2];
+        const R tq = l0 * to[0] + l1 * to[1] + l2 * to[2];
+        const R fl = up[q] * ti + um[q] * tq;
+        res[f][o] -= l0 * fl;
+        res[f][o + 1] -= l1 * fl;
+        res[f][o + 2] -= l2 * fl;
+      }
+    }
+  }
+
+  // ---------------- M^-1 and the stage combination ----------------
+  // Mz = J_h/120 * m, m_aa = 3 dz_a + dz_b + dz_c, m_ab = dz_a + dz_b + dz_c / 2.
+  const R m00 = R(3) * dz[0] + dz[1] + dz[2];
+  const R m11 = dz[0] + R(3) * dz[1] + dz[2];
+  const R m22 = dz[0] + dz[1] + R(3) * dz[2];
+  const R m01 = dz[0] + dz[1] + R(0.5) * dz[2];
+  const R m02 = dz[0] + dz[2] + R(0.5) * dz[1];
+  const R m12 = dz[1] + dz[2] + R(0.5) * dz[0];
+  const R c00 = m11 * m22 - m12 * m12;
+  const R c01 = m02 * m12 - m01 * m22;
+  const R c02 = m01 * m12 - m02 * m11;
+  const R c11 = m00 * m22 - m02 * m02;
+  const R c12 = m01 * m02 - m00 * m12;
+  const R c22 = m00 * m11 - m01 * m01;
+  const R det = m00 * c00 + m01 * c01 + m02 * c02;
+  const R sc = R(120) / (Jh * det);  // Mz^-1 = sc * cofactor matrix
+
+  const R* __restrict__ Tn = static_cast<const R*>(a.Tn);
+  R* __restrict__ Out = static_cast<R*>(a.Tout);
+  const R dt = R(a.dt), ca = R(a.a), cb = R(a.b);
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const R ht[3] = {R(2) * res[f][0] - res[f][3], R(2) * res[f][1] - res[f][4],
+                     R(2) * res[f][2] - res[f][5]};
+    const R hb[3] = {R(2) * res[f][3] - res[f][0], R(2) * res[f][4] - res[f][1],
+                     R(2) * res[f][5] - res[f][2]};
+    R L[6];
+    L[0] = sc * (c00 * ht[0] + c01 * ht[1] + c02 * ht[2]);
+    L[1] = sc * (c01 * ht[0] + c11 * ht[1] + c12 * ht[2]);
+    L[2] = sc * (c02 * ht[0] + c12 * ht[1] + c22 * ht[2]);
+    L[3] = sc * (c00 * hb[0] + c01 * hb[1] + c02 * hb[2]);
+    L[4] = sc * (c01 * hb[0] + c11 * hb[1] + c12 * hb[2]);
+    L[5] = sc * (c02 * hb[0] + c12 * hb[1] + c22 * hb[2]);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const size_t idx = (size_t)(f * 6 + i) * S + p;
+      R out;
+      if (RHS) {
+        out = L[i];
+      } else {
+        out = cb * (T[f][i] + dt * L[i]);
+        if (READ_TN) out += ca * Tn[idx];
+      }
+      Out[idx] = out;
+    }
+  }
+}
+
+template <typename R, int NF>
+hipError_t launch_nf(const StageArgs& a, bool w_zero, bool rhs_only, bool read_tn, hipStream_t s) {
+  dim3 grid(a.n_tiles), block(256);
+  if (rhs_only) {
+    if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<R, NF, false, true, false>), grid, block, 0, s, a);
+  } else if (read_tn) {
+    if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<R, NF, false, false, true>), grid, block, 0, s, a);
+  } else {
+    if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, false, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<R, NF, false, false, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_r(const StageArgs& a, bool w_zero, bool rhs_only, bool read_tn, hipStream_t s) {
+  switch (a.n_fields) {
+    case 1: return launch_nf<R, 1>(a, w_zero, rhs_only, read_tn, s);
+    case 2: return launch_nf<R, 2>(a, w_zero, rhs_only, read_tn, s);
+    case 3: return launch_nf<R, 3>(a, w_zero, rhs_only, read_tn, s);
+    case 4: return launch_nf<R, 4>(a, w_zero, rhs_only, read_tn, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only, bool read_tn,
+                        hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  return fp32 ? launch_r<float>(a, w_zero, rhs_only, read_tn, s)
+              : launch_r<double>(a, w_zero, rhs_only, read_tn, s);
+}
+
+}  // namespace sdg

@@ -1,0 +1,230 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Metric: per field, ||x_gpu - x_oracle||_inf / ||x_oracle||_inf on live
+prisms (element-wise relative error is meaningless where fluxes cancel).
+FP64 bar: 1e-12.  Inputs are seeded and synthetic; no oracle input or
+expected value comes from the GPU.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2605_16082_amd as P
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def rel_err(got, ref):
+    F = ref.shape[0]
+    num = np.abs(got - ref).reshape(F, -1).max(axis=1)
+    den = np.abs(ref).reshape(F, -1).max(axis=1)
+    return num / np.maximum(den, 1e-300)
+
+
+def _random_velocity(w, seed=5, with_w=True):
+    rng = np.random.default_rng([seed, 7])
+    U = w.U + 0.05 * rng.standard_normal(w.U.shape)     # discontinuous across prisms
+    if with_w:
+        U[2] = 1e-3 * rng.standard_normal(U[2].shape)
+    else:
+        U[2] = 0.0
+    return U
+
+
+_CASES = {}
+
+
+def case(name):
+    """(workload, oracle mesh) built once per session."""
+    if name not in _CASES:
+        if name == "tiny":
+            w = W.tiny(n_fields=2)
+        elif name == "config1":
+            w = W.config1()
+        elif name == "ragged":
+            w = W.ragged()
+        elif name == "wnonzero":
+            w = W.config1(n=7, n_layers=4)
+            w.U = _random_velocity(w)
+            w.w_is_zero = False
+        elif name == "single":
+            # one triangle, one layer: every face open
+            w = W.tiny(n=1, n_layers=1)
+            keep = np.array([0])
+            w = W.Workload("single", w.vxy, w.tri[keep], np.full((1, 3), -1, np.int32),
+                           w.nlayers[keep], w.zlev[:2], w.U[:, :, :1], w.T0[:, :, :1],
+                           w.kappa[:1], w.dt, np.array([0.4]))
+        elif name == "deep_ragged":
+            w = W.ragged(seed=3, n=9, n_min=1, n_max=37, depth_max=190.0, n_fields=3)
+        else:
+            raise KeyError(name)
+        _CASES[name] = (w, O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev))
+    return _CASES[name]
+
+
+def upload(w, precision=P.SDG_FP64):
+    s, U, kappa, state = P.from_workload(w, precision)
+    return s, U, kappa, state
+
+
+@pytest.mark.parametrize("name", ["tiny", "single", "config1", "ragged", "wnonzero", "deep_ragged"])
+def test_rhs_3d_parity(name):
+    w, m = case(name)
+    s, U, kappa, state = upload(w)
+    L = s.rhs_3d(state)
+    s.sync()
+    got = s.gather(L)
+    ref = O.explicit_operator(m, w.U, w.T0, w.t_ext)
+    err = rel_err(got, ref)
+    print(name, "rhs rel err per field", err)
+    assert np.all(err <= TOL64), err
+
+
+@pytest.mark.parametrize("name", ["config1", "ragged", "wnonzero"])
+def test_rk_stage_parity(name):
+    w, m = case(name)
+    s, U, kappa, state = upload(w)
+    rng = np.random.default_rng([11, len(name)])
+    Ts_np = w.T0 + 0.1 * rng.standard_normal(w.T0.shape)
+    Ts = s.scatter(Ts_np)
+    for stage in range(3):
+        out = s.rk_stage(stage, state, Ts)
+        s.sync()
+        got = s.gather(out)
+        ref = O.rk_stage(m, w.U, stage, w.T0, Ts_np, w.dt, w.t_ext)
+        err = rel_err(got, ref)
+        print(name, "stage", stage, err)
+        assert np.all(err <= TOL64), (stage, err)
+
+
+@pytest.mark.parametrize("name", ["tiny", "single", "config1", "ragged", "deep_ragged"])
+def test_vertical_solve_parity(name):
+    w, m = case(name)
+    s, U, kappa, state = upload(w)
+    for dt in (w.dt, 50.0 * w.dt):
+        s.set_params(dt, w.t_ext, w.penalty, w.w_is_zero)
+        out = s.vertical_implicit_solve(state)
+        s.sync()
+        got = s.gather(out)
+        ref = O.implicit_solve(m, w.kappa, dt, w.T0, w.penalty)
+        err = rel_err(got, ref)
+        print(name, "dt", dt, "solve", err)
+        assert np.all(err <= TOL64), err
+    # in place (output aliases input)
+    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero)
+    tmp = state.clone()
+    s.vertical_implicit_solve(tmp, tmp)
+    s.sync()
+    ref = O.implicit_solve(m, w.kappa, w.dt, w.T0, w.penalty)
+    assert np.all(rel_err(s.gather(tmp), ref) <= TOL64)
+
+
+@pytest.mark.parametrize("name,n_steps", [("config1", 10), ("ragged", 4), ("wnonzero", 3)])
+def test_step_parity(name, n_steps):
+    w, m = case(name)
+    s, U, kappa, state = upload(w)
+    s.step(n_steps)
+    s.sync()
+    got = s.gather(state)
+    ref = w.T0
+    for _ in range(n_steps):
+        ref = O.step(m, w.U, w.kappa, ref, w.dt, w.t_ext, w.penalty)
+    err = rel_err(got, ref)
+    print(name, n_steps, "steps", err)
+    assert np.all(err <= TOL64), err
+
+
+@pytest.mark.parametrize("name", ["config1", "ragged", "deep_ragged"])
+def test_mass_parity(name):
+    w, m = case(name)
+    s, U, kappa, state = upload(w)
+    got = s.mass(state)[0]
+    ref = O.mass(m, w.T0)
+    assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref)), (got, ref)
+
+
+def test_step_is_deterministic():
+    w, m = case("config1")
+    a = upload(w)
+    b = upload(w)
+    a[0].step(3)
+    b[0].step(3)
+    a[0].sync()
+    b[0].sync()
+    assert np.array_equal(a[0].gather(a[3]), b[0].gather(b[3]))
+
+
+def test_check_finite_reports_nan():
+    w, m = case("tiny")
+    s, U, kappa, state = upload(w)
+    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, check_finite=True)
+    s.step(1)
+    bad = w.T0.copy()
+    bad[0, 2, 5] = np.nan
+    s.scatter(bad, out=state)
+    with pytest.raises(P.SlimDGError) as e:
+        s.step(1)
+    assert e.value.status == -6
+
+
+@pytest.mark.parametrize("name", ["config1", "ragged"])
+def test_fp32_state_form(name):
+    """FP32 state/fluxes with the FP64 column solve: bounded error vs the
+    FP64 oracle after a few steps, and mass sums in FP64."""
+    w, m = case(name)
+    s, U, kappa, state = upload(w, P.SDG_FP32_STATE_FP64_SOLVE)
+    L = s.rhs_3d(state)
+    s.sync()
+    err = rel_err(s.gather(L), O.explicit_operator(m, w.U, w.T0, w.t_ext))
+    print(name, "fp32 rhs", err)
+    assert np.all(err <= 5e-5), err
+    s.step(3)
+    s.sync()
+    ref = w.T0
+    for _ in range(3):
+        ref = O.step(m, w.U, w.kappa, ref, w.dt, w.t_ext, w.penalty)
+    err = rel_err(s.gather(state), ref)
+    print(name, "fp32 3 steps", err)
+    assert np.all(err <= 2e-5), err
+
+
+@pytest.fixture(scope="module")
+def big():
+    w = W.config2()
+    m = O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
+    return w, m
+
+
+@pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32_STATE_FP64_SOLVE])
+def test_config2_sampled_parity(big, precision):
+    """Full-size config (199,712 columns x 30 layers, 4 fields) in the launch
+    configuration the benchmark times, checked on sampled prisms/columns."""
+    w, m = big
+    s, U, kappa, state = upload(w, precision)
+    tol = TOL64 if precision == P.SDG_FP64 else 5e-5
+    rng = np.random.default_rng([2, 9])
+    Ts_np = w.T0 + 0.05 * rng.standard_normal(w.T0.shape)
+    Ts = s.scatter(Ts_np)
+    sample = np.sort(rng.choice(m.P, 3000, replace=False))
+    slots = s.slots[sample]
+    for stage in range(3):
+        out = s.rk_stage(stage, state, Ts)
+        s.sync()
+        got = out[:, :, slots].double().cpu().numpy()
+        ref = O.rk_stage(m, w.U, stage, w.T0, Ts_np, w.dt, w.t_ext, prisms=sample)
+        err = rel_err(got, ref)
+        print("config2 stage", stage, err)
+        assert np.all(err <= tol), (stage, err)
+    cols = np.sort(rng.choice(m.C, 200, replace=False))
+    out = s.vertical_implicit_solve(Ts)
+    s.sync()
+    ref_full = O.implicit_solve(m, w.kappa, w.dt, Ts_np, w.penalty, columns=cols)
+    pr = (m.off[cols][:, None] + np.arange(30)[None, :]).ravel()
+    got = out[:, :, s.slots[pr]].double().cpu().numpy()
+    err = rel_err(got, ref_full[:, :, pr])
+    print("config2 solve", err)
+    assert np.all(err <= (TOL64 if precision == P.SDG_FP64 else 5e-5)), err
