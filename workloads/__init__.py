@@ -17,6 +17,8 @@ from .prism_mesh import (  # noqa: F401
     cfl_dt,
     config1,
     config2,
+    config4,
+    small_ensemble,
     tiny,
     ragged,
     natural_prism_count,

@@ -175,9 +175,10 @@ def zlevel_levels(vxy, tri, depth_c, dz: float, n_min: int, n_max: int):
     """Flat z-levels -k*dz; column t gets clamp(ceil(depth_c[t]/dz), n_min, n_max)
     layers (stair-step bottom)."""
     nl = np.clip(np.ceil(depth_c / dz), n_min, n_max).astype(np.int32)
-    parts = [np.repeat((-dz * np.arange(n + 1, dtype=np.float64))[:, None], 3, 1)
-             for n in nl]
-    return nl, np.concatenate(parts, axis=0)
+    rows = (nl + 1).astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(rows)[:-1]])
+    k = np.arange(int(rows.sum()), dtype=np.int64) - np.repeat(start, rows)
+    return nl, np.repeat((-dz * k.astype(np.float64))[:, None], 3, axis=1)
 
 
 def prism_node_xyz(vxy, tri, nlayers, zlev):
@@ -210,13 +211,16 @@ def rotation_rate(L: float = DOMAIN_L, umax: float = 0.5) -> float:
 def solid_body_velocity(x, y, L: float = DOMAIN_L, umax: float = 0.5):
     """Nodal (u, v, w) of the rotation u = -w (y-L/2), v = w (x-L/2), w = 0."""
     om = rotation_rate(L, umax)
-    u = -om * (y - 0.5 * L)
-    v = om * (x - 0.5 * L)
-    return np.stack([u, v, np.zeros_like(u)])
+    out = np.empty((3,) + np.shape(x), dtype=np.float64)
+    np.multiply(y - 0.5 * L, -om, out=out[0])
+    np.multiply(x - 0.5 * L, om, out=out[1])
+    out[2] = 0.0
+    return out
 
 
-def cfl_dt(vxy, tri, U, cfl: float = 0.3) -> float:
-    """dt = cfl * min_K d_K / max|U| with d_K = 4 area / perimeter."""
+def cfl_dt(vxy, tri, U=None, cfl: float = 0.3, umax: float | None = None) -> float:
+    """dt = cfl * min_K d_K / max|U| with d_K = 4 area / perimeter (max|U|
+    over the nodal velocity U, or given as ``umax``)."""
     p = vxy[tri]
     e0 = p[:, 1] - p[:, 0]
     e1 = p[:, 2] - p[:, 1]
@@ -225,7 +229,8 @@ def cfl_dt(vxy, tri, U, cfl: float = 0.3) -> float:
     per = (np.hypot(e0[:, 0], e0[:, 1]) + np.hypot(e1[:, 0], e1[:, 1])
            + np.hypot(e2[:, 0], e2[:, 1]))
     d = 4.0 * area / per
-    umax = float(np.sqrt((U ** 2).sum(axis=0)).max())
+    if umax is None:
+        umax = float(np.sqrt(np.einsum("cip,cip->ip", U, U)).max())
     return float(cfl * d.min() / umax)
 
 
@@ -315,3 +320,71 @@ def ragged(seed: int = 0, n: int = 12, n_fields: int = 2, dz: float = 5.0,
     kappa = np.geomspace(1e-2, 1e-5, int(nl.max()))
     return Workload("ragged", vxy, tri, nbr, nl, zlev, U, T0, kappa=kappa,
                     dt=cfl_dt(vxy, tri, U), t_ext=np.linspace(0.5, 1.5, n_fields))
+
+
+def _concat_members(parts):
+    """Concatenate independent member meshes (disjoint vertex and column ids)."""
+    vxy, tri, nbr, nl, zl, moff = [], [], [], [], [], [0]
+    voff = coff = 0
+    for (v, t, nb, n, z) in parts:
+        vxy.append(v)
+        tri.append(t + voff)
+        nbr.append(np.where(nb >= 0, nb + coff, -1))
+        nl.append(n)
+        zl.append(z)
+        voff += len(v)
+        coff += len(t)
+        moff.append(coff)
+    return (np.concatenate(vxy), np.concatenate(tri).astype(np.int32),
+            np.concatenate(nbr).astype(np.int32), np.concatenate(nl).astype(np.int32),
+            np.concatenate(zl), np.array(moff, dtype=np.int32))
+
+
+def config4(seed: int = 0, n_members: int = 16, n_lo: int = 100, n_hi: int = 244,
+            dz: float = 5.0, n_min: int = 5, n_max: int = 60, with_fields: bool = True) -> Workload:
+    """Batched form: independently seeded members (member m uses seed 1000 + m)
+    of n ~ U{n_lo..n_hi} split squares (about 20k-120k triangles each), flat
+    z-levels every dz metres, column depth h_c = 25 + 275 g(x, y) at the
+    centroid (g a seeded smooth field in [0, 1]), layer count
+    clamp(ceil(h_c/dz), n_min, n_max); stair-step bottom (steps are walls).
+    Four fields as in config2 (temperature linear in depth over 300 m)."""
+    parts = []
+    for m in range(n_members):
+        ms = 1000 + seed * 100 + m
+        n = int(np.random.default_rng([ms, 5]).integers(n_lo, n_hi + 1))
+        v, t, nb = square_mesh(n, seed=ms)
+        cxy = v[t].mean(axis=1)
+        depth = 25.0 + 275.0 * smooth_field(cxy[:, 0], cxy[:, 1], ms)
+        nl, zl = zlevel_levels(v, t, depth, dz, n_min, n_max)
+        parts.append((v, t, nb, nl, zl))
+    vxy, tri, nbr, nl, zl, moff = _concat_members(parts)
+    x, y, z = prism_node_xyz(vxy, tri, nl, zl)
+    U = solid_body_velocity(x, y)
+    vel_v = solid_body_velocity(vxy[:, 0], vxy[:, 1])
+    umax = float(np.hypot(vel_v[0], vel_v[1]).max())
+    del x, y
+    if with_fields:
+        rng = np.random.default_rng([seed, 6])
+        temp = 25.0 + 15.0 * z / 300.0 + rng.uniform(-0.1, 0.1, size=z.shape)
+        salt = 35.0 + rng.uniform(-0.5, 0.5, size=z.shape)
+        T0 = np.empty((4,) + z.shape)
+        T0[0], T0[1], T0[2], T0[3] = U[0], U[1], temp, salt
+    else:
+        T0 = np.zeros((4,) + z.shape)
+    lvl = np.arange(n_max, dtype=np.float64)
+    kappa = 10.0 ** (-2.0 - 3.0 * lvl / (n_max - 1))
+    return Workload("config4", vxy, tri, nbr, nl, zl, U, T0, kappa=kappa,
+                    dt=cfl_dt(vxy, tri, umax=umax), t_ext=np.array([0.0, 0.0, 17.5, 35.0]),
+                    n_steps=50, member_tri_off=moff)
+
+
+def small_ensemble(seed: int = 0, n_members: int = 3, n_lo: int = 6, n_hi: int = 10,
+                   n_fields: int = 2) -> Workload:
+    """A few small z-level members (test-sized batched form)."""
+    w = config4(seed=seed, n_members=n_members, n_lo=n_lo, n_hi=n_hi, dz=10.0, n_min=2, n_max=12)
+    rng = np.random.default_rng([seed, 8])
+    T0 = 1.0 + rng.uniform(-0.5, 0.5, size=(n_fields, 6, w.n_prisms))
+    return Workload("ensemble", w.vxy, w.tri, w.nbr, w.nlayers, w.zlev, w.U, T0,
+                    kappa=np.geomspace(1e-2, 1e-5, int(w.nlayers.max())), dt=w.dt,
+                    t_ext=np.linspace(0.0, 1.0, n_fields), n_steps=5,
+                    member_tri_off=w.member_tri_off)
