@@ -186,6 +186,52 @@ sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
  * Synchronises the stream. */
 sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
+/* Launch shape of the fused stage kernel.  Results do not depend on it.
+ * tile_layers: layers per workgroup of 64 columns (1, 2 or 4; default 4);
+ * xcd_remap: 1 = give each XCD one contiguous range of cells (default). */
+typedef struct {
+  int32_t tile_layers;
+  int32_t xcd_remap;
+} sdg_tuning;
+
+sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out);
+sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* tuning);
+
+/* Time every stage-kernel launch shape (reps launches of stage 1 each, on the
+ * set fields and velocity, writing a workspace stage buffer) and keep the
+ * fastest.  Synchronises the stream.  `chosen` may be NULL. */
+sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen);
+
+/* Capture one sdg_step (three stages and the column solve, on the set fields)
+ * into a HIP graph; replaces any previous capture.  Waits for the context
+ * stream first.  Any later set_* / set_tuning / mesh_upload call invalidates
+ * the capture (sdg_graph_launch then returns SDG_E_STATE). */
+sdg_status sdg_graph_capture_step(sdg_ctx* ctx);
+
+/* Replay the captured step n_steps times on the context stream. */
+sdg_status sdg_graph_launch(sdg_ctx* ctx, int n_steps);
+
+/* Y = M X (inverse = 0) or Y = M^-1 X (inverse != 0), prism by prism, for a
+ * [n_fields][6][n_slots] array in the state precision.  Y may alias X. */
+sdg_status sdg_apply_mass(sdg_ctx* ctx, const void* dev_X, void* dev_Y, int inverse);
+
+/* host_out[m * n_fields + f] = sum over member m's prisms of X_f^T M Y_f
+ * (FP64, fixed summation order).  Synchronises the stream. */
+sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double* host_out);
+
+/* Reverse of one sdg_step (FP64 contexts only), in the variable Z = M^-1 lambda
+ * where lambda = dJ/dx is the adjoint state:
+ *   mu     = (M - dt A^T)^-1 M Z^{n+1}                     (transposed column solve)
+ *   dkappa[l] += dt mu^T (dA/dkappa_l) x^{n+1}              (if dev_dkappa != NULL)
+ *   Z^n    = reverse SSP-RK3 stages with M^-1 R_lin^T       (R_lin: the advective
+ *            residual without the exterior inflow values)
+ * so that lambda^n = M Z^n.  dev_z_next, dev_z_out: [n_fields][6][n_slots]
+ * doubles (may alias); dev_x_next: the state after the forward step being
+ * reversed; dev_dkappa: [max_layers] doubles, accumulated.  Uses the
+ * workspace stage buffers. */
+sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_next,
+                            double* dev_dkappa);
+
 /* Wait for the context's stream and report any asynchronous HIP error. */
 sdg_status sdg_sync(sdg_ctx* ctx);
 

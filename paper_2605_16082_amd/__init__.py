@@ -13,6 +13,11 @@ from .slimdg import (  # noqa: F401
     Mesh,
     SlimDG,
     SlimDGError,
+    Tuning,
     from_workload,
     load_library,
+)
+from .autograd import (  # noqa: F401
+    MNorm,
+    TracerSteps,
 )

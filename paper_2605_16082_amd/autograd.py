@@ -1,0 +1,80 @@
+"""torch.autograd wrappers of the tracer step and its hand-written adjoint.
+
+``TracerSteps.apply(T0, kappa, model, n_steps, checkpoint_every)`` advances
+``T0`` by ``n_steps`` library steps and returns the final state.  Its backward
+runs the library's adjoint step in reverse: the forward pass keeps only every
+``checkpoint_every``-th state; each segment is recomputed from its checkpoint
+(storing the post-solve states it needs) and then reversed step by step.  The
+adjoint state is carried as Z = M^-1 lambda; the returned gradients are
+dJ/dT0 = M Z_0 and dJ/dkappa (per layer).
+
+``MNorm.apply(x, model)`` is J = sqrt(sum_f x_f^T M x_f), whose gradient is
+M x / J.  Both use only library kernels on the device.
+"""
+
+from __future__ import annotations
+
+import math
+
+import torch
+
+
+class TracerSteps(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, T0, kappa, model, n_steps: int, checkpoint_every: int = 20):
+        if model.dtype != torch.float64:
+            raise ValueError("the adjoint needs an FP64 model")
+        kap = kappa.detach().contiguous()
+        model.set_diffusivity(kap)
+        state = T0.detach().clone()
+        model.set_fields(state)
+        ckpts = []
+        done = 0
+        while done < n_steps:
+            ckpts.append(state.clone())
+            k = min(checkpoint_every, n_steps - done)
+            model.step(k)
+            done += k
+        ctx.model = model
+        ctx.ckpts = ckpts
+        ctx.n_steps = n_steps
+        ctx.every = checkpoint_every
+        ctx.kappa = kap
+        return state
+
+    @staticmethod
+    def backward(ctx, grad_xN):
+        s = ctx.model
+        s.set_diffusivity(ctx.kappa)
+        z = s.apply_mass(grad_xN.contiguous(), inverse=True)
+        dk = torch.zeros_like(ctx.kappa)
+        for i in range(len(ctx.ckpts) - 1, -1, -1):
+            start = i * ctx.every
+            k = min(ctx.every, ctx.n_steps - start)
+            st = ctx.ckpts[i].clone()
+            s.set_fields(st)
+            xs = []
+            for _ in range(k):
+                s.step(1)
+                xs.append(st.clone())
+            for j in range(k - 1, -1, -1):
+                s.step_adjoint(z, z, xs[j], dk)
+        grad_T0 = s.apply_mass(z)
+        return grad_T0, dk, None, None, None
+
+
+class MNorm(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x, model):
+        v = float(model.m_dot(x, x).sum())
+        J = math.sqrt(v)
+        ctx.model = model
+        ctx.save_for_backward(x)
+        ctx.J = J
+        return torch.tensor(J, dtype=torch.float64, device=x.device)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (x,) = ctx.saved_tensors
+        g = ctx.model.apply_mass(x.contiguous())
+        return g * (gJ / ctx.J), None

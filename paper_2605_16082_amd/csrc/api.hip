@@ -45,11 +45,11 @@ struct Plan {
   int64_t n_prisms = 0, n_slots = 0, n_lslots = 0;
   std::vector<int32_t> cell_base, cell_lbase, cell_depth, member_off;
   std::vector<int64_t> zoff;  // per column: first row of its levels in desc.zlev
-  int n_tiles = 0;
+  int n_tiles[kTileChoices] = {0, 0, 0};
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_col_member, o_member_off,
-      o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles, o_stage_a, o_stage_b, o_scratch, o_colmass,
-      o_msum, o_flag, total;
+      o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_stage_a, o_stage_b, o_scratch,
+      o_colmass, o_msum, o_flag, o_kpart, total;
   size_t state_bytes, velocity_bytes;
 };
 
@@ -142,7 +142,7 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.cell_lbase.assign(P.n_cells + 1, 0);
   P.cell_depth.assign(P.n_cells, 0);
   int64_t sb = 0, lb = 0;
-  P.n_tiles = 0;
+  for (int t = 0; t < kTileChoices; ++t) P.n_tiles[t] = 0;
   for (int k = 0; k < P.n_cells; ++k) {
     int depth = 0;
     for (int c = k * kCell; c < std::min(C, (k + 1) * kCell); ++c) depth = std::max(depth, (int)d->nlayers[c]);
@@ -151,13 +151,19 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
     P.cell_lbase[k] = (int32_t)lb;
     sb += (int64_t)depth * kCell;
     lb += (int64_t)(depth + 1) * kCell;
-    P.n_tiles += (depth + kTileLayers - 1) / kTileLayers;
+    for (int t = 0; t < kTileChoices; ++t)
+      P.n_tiles[t] += (depth + kTileLayerOptions[t] - 1) / kTileLayerOptions[t];
     if (sb > INT32_MAX / 2 || lb > INT32_MAX / 2) return fail(SDG_E_UNSUPPORTED, "mesh too large for 32-bit slot indices");
   }
   P.cell_base[P.n_cells] = (int32_t)sb;
   P.cell_lbase[P.n_cells] = (int32_t)lb;
   P.n_slots = sb;
   P.n_lslots = lb;
+  // kernels address a field's 6 node rows (and the velocity's) with 32-bit
+  // byte offsets
+  if ((uint64_t)6 * (uint64_t)sb * 8u >= ((uint64_t)1 << 32) || (uint64_t)3 * (uint64_t)lb * 8u >= ((uint64_t)1 << 32))
+    return fail(SDG_E_UNSUPPORTED, "mesh has %lld prism slots; at most %lld are supported", (long long)sb,
+                (long long)((((uint64_t)1 << 32) - 1) / 48));
 
   // workspace
   const size_t es = P.fp32 ? 4 : 8;
@@ -177,13 +183,14 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_xy = take(sizeof(double) * 6 * P.CS);
   P.o_zl = take(sizeof(double) * 3 * (size_t)P.n_lslots);
   P.o_zl32 = take(sizeof(float) * 3 * (size_t)P.n_lslots);
-  P.o_tiles = take(sizeof(WgTile) * std::max(P.n_tiles, 1));
+  for (int t = 0; t < kTileChoices; ++t) P.o_tiles[t] = take(sizeof(WgTile) * std::max(P.n_tiles[t], 1));
   P.o_stage_a = take(P.state_bytes);
   P.o_stage_b = take(P.state_bytes);
   P.o_scratch = take(sizeof(double) * (size_t)(18 + 6 * P.F) * (size_t)P.n_slots);
   P.o_colmass = take(sizeof(double) * (size_t)P.F * P.CS);
   P.o_msum = take(sizeof(double) * (size_t)P.F * P.n_members);
   P.o_flag = take(sizeof(int32_t) * 64);
+  P.o_kpart = take(sizeof(double) * (size_t)P.max_layers * (size_t)P.n_cells);
   P.total = o;
   return SDG_OK;
 }
@@ -211,11 +218,20 @@ struct sdg_ctx {
   Plan plan;
   DevMesh dm{};
   char* ws = nullptr;
-  WgTile* tiles = nullptr;
+  WgTile* tiles[kTileChoices] = {nullptr, nullptr, nullptr};
+  // launch shape of the stage kernel (chosen by sdg_set_tuning / sdg_autotune)
+  int tile_choice = 2;   // index into kTileLayerOptions (4 layers)
+  int xcd = 1;
+  // captured step
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool graph_valid = false;
   int32_t* member_off_dev = nullptr;
   double* colmass = nullptr;
   double* msum = nullptr;
   int32_t* flag = nullptr;
+  double* kpart = nullptr;
   void* stage_a = nullptr;
   void* stage_b = nullptr;
   double* scratch = nullptr;
@@ -283,7 +299,23 @@ sdg_status sdg_create(sdg_ctx** out, int device, void* hip_stream) {
   return SDG_OK;
 }
 
+namespace {
+void drop_graph(sdg_ctx* ctx) {
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->graph_exec = nullptr;
+  ctx->graph = nullptr;
+  ctx->graph_valid = false;
+}
+}  // namespace
+
 sdg_status sdg_destroy(sdg_ctx* ctx) {
+  if (!ctx) return SDG_OK;
+  {
+    DeviceGuard g(ctx->device);
+    drop_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  }
   delete ctx;
   return SDG_OK;
 }
@@ -291,6 +323,7 @@ sdg_status sdg_destroy(sdg_ctx* ctx) {
 sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_workspace, size_t ws_bytes) {
   if (!ctx) return fail(SDG_E_ARG, "context is NULL");
   ctx->have_mesh = false;
+  ctx->graph_valid = false;
   ctx->U = nullptr;
   ctx->kappa = nullptr;
   ctx->state = nullptr;
@@ -306,10 +339,12 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   // host images of the device tables
   std::vector<int32_t> nlay(CS, 0), nbr_slot(3 * (size_t)CS, -1), nbr_meta(3 * (size_t)CS, 0), colmem(CS, -1);
   std::vector<double> xy(6 * (size_t)CS, 0.0), zl(3 * (size_t)P.n_lslots, 0.0);
-  std::vector<WgTile> tiles;
-  tiles.reserve(P.n_tiles);
-  for (int k = 0; k < P.n_cells; ++k)
-    for (int l0 = 0; l0 < P.cell_depth[k]; l0 += kTileLayers) tiles.push_back({k, l0});
+  std::vector<WgTile> tiles[kTileChoices];
+  for (int t = 0; t < kTileChoices; ++t) {
+    tiles[t].reserve(P.n_tiles[t]);
+    for (int k = 0; k < P.n_cells; ++k)
+      for (int l0 = 0; l0 < P.cell_depth[k]; l0 += kTileLayerOptions[t]) tiles[t].push_back({k, l0});
+  }
   for (int m = 0; m < P.n_members; ++m)
     for (int c = P.member_off[m]; c < P.member_off[m + 1]; ++c) colmem[c] = m;
   for (int c = 0; c < C; ++c) {
@@ -349,7 +384,9 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
       {P.o_member_off, P.member_off.data(), sizeof(int32_t) * P.member_off.size()},
       {P.o_xy, xy.data(), sizeof(double) * xy.size()},
       {P.o_zl, zl.data(), sizeof(double) * zl.size()},
-      {P.o_tiles, tiles.data(), sizeof(WgTile) * tiles.size()},
+      {P.o_tiles[0], tiles[0].data(), sizeof(WgTile) * tiles[0].size()},
+      {P.o_tiles[1], tiles[1].data(), sizeof(WgTile) * tiles[1].size()},
+      {P.o_tiles[2], tiles[2].data(), sizeof(WgTile) * tiles[2].size()},
   };
   for (const Cp& cp : cps) {
     if (cp.bytes == 0) continue;
@@ -383,11 +420,12 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   ctx->plan = std::move(P);
   const Plan& Q = ctx->plan;
   ctx->ws = ws;
-  ctx->tiles = reinterpret_cast<WgTile*>(ws + Q.o_tiles);
+  for (int t = 0; t < kTileChoices; ++t) ctx->tiles[t] = reinterpret_cast<WgTile*>(ws + Q.o_tiles[t]);
   ctx->member_off_dev = reinterpret_cast<int32_t*>(ws + Q.o_member_off);
   ctx->colmass = reinterpret_cast<double*>(ws + Q.o_colmass);
   ctx->msum = reinterpret_cast<double*>(ws + Q.o_msum);
   ctx->flag = reinterpret_cast<int32_t*>(ws + Q.o_flag);
+  ctx->kpart = reinterpret_cast<double*>(ws + Q.o_kpart);
   ctx->stage_a = ws + Q.o_stage_a;
   ctx->stage_b = ws + Q.o_stage_b;
   ctx->scratch = reinterpret_cast<double*>(ws + Q.o_scratch);
@@ -411,6 +449,7 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
   ctx->eta = eta;
   ctx->w_zero = p->w_is_zero != 0;
   ctx->check_finite = p->check_finite != 0;
+  ctx->graph_valid = false;
   ctx->have_params = true;
   g_err.clear();
   return SDG_OK;
@@ -420,6 +459,7 @@ sdg_status sdg_set_velocity(sdg_ctx* ctx, const void* dev_uvw) {
   if (!ctx || !dev_uvw) return fail(SDG_E_ARG, "context or velocity is NULL");
   if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_velocity needs an uploaded mesh");
   ctx->U = dev_uvw;
+  ctx->graph_valid = false;
   g_err.clear();
   return SDG_OK;
 }
@@ -428,6 +468,7 @@ sdg_status sdg_set_diffusivity(sdg_ctx* ctx, const double* dev_kappa) {
   if (!ctx || !dev_kappa) return fail(SDG_E_ARG, "context or diffusivity is NULL");
   if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_diffusivity needs an uploaded mesh");
   ctx->kappa = dev_kappa;
+  ctx->graph_valid = false;
   g_err.clear();
   return SDG_OK;
 }
@@ -436,6 +477,7 @@ sdg_status sdg_set_fields(sdg_ctx* ctx, void* dev_state) {
   if (!ctx || !dev_state) return fail(SDG_E_ARG, "context or state is NULL");
   if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_fields needs an uploaded mesh");
   ctx->state = dev_state;
+  ctx->graph_valid = false;
   g_err.clear();
   return SDG_OK;
 }
@@ -453,8 +495,10 @@ sdg_status check_explicit(sdg_ctx* ctx, const char* who) {
 StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, double a, double b) {
   StageArgs s{};
   s.m = ctx->dm;
-  s.tiles = ctx->tiles;
-  s.n_tiles = ctx->plan.n_tiles;
+  s.tiles = ctx->tiles[ctx->tile_choice];
+  s.n_tiles = ctx->plan.n_tiles[ctx->tile_choice];
+  s.tile_layers = kTileLayerOptions[ctx->tile_choice];
+  s.xcd = ctx->xcd;
   s.n_fields = ctx->plan.F;
   s.Tn = Tn;
   s.Ts = Ts;
@@ -469,14 +513,15 @@ StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, d
 
 constexpr double kRk[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
 
-sdg_status enqueue_stage(sdg_ctx* ctx, int stage, const void* Tn, const void* Ts, void* Tout) {
+sdg_status enqueue_stage(sdg_ctx* ctx, int stage, const void* Tn, const void* Ts, void* Tout,
+                         hipStream_t strm) {
   StageArgs s = stage_args(ctx, Tn, Ts, Tout, kRk[stage][0], kRk[stage][1]);
-  hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, false, stage > 0, ctx->stream);
+  hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, false, stage > 0, strm);
   if (e != hipSuccess) return hip_fail(e, "rk_stage launch");
   return SDG_OK;
 }
 
-sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout) {
+sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, hipStream_t strm) {
   SolveArgs a{};
   a.m = ctx->dm;
   a.n_fields = ctx->plan.F;
@@ -486,9 +531,22 @@ sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout) {
   a.scratch = ctx->scratch;
   a.dt = ctx->dt;
   a.eta = ctx->eta;
-  hipError_t e = launch_vsolve(a, ctx->plan.fp32, ctx->stream);
+  hipError_t e = launch_vsolve(a, ctx->plan.fp32, strm);
   if (e != hipSuccess) return hip_fail(e, "vertical solve launch");
   return SDG_OK;
+}
+
+// One step on the set fields: three stages through the two workspace stage
+// buffers, then the column solve back into the state.
+sdg_status enqueue_step(sdg_ctx* ctx, hipStream_t strm) {
+  void* X = ctx->state;
+  void* A = ctx->stage_a;
+  void* B = ctx->stage_b;
+  sdg_status st;
+  if ((st = enqueue_stage(ctx, 0, nullptr, X, A, strm)) != SDG_OK) return st;
+  if ((st = enqueue_stage(ctx, 1, X, A, B, strm)) != SDG_OK) return st;
+  if ((st = enqueue_stage(ctx, 2, X, B, A, strm)) != SDG_OK) return st;
+  return enqueue_solve(ctx, A, X, strm);
 }
 
 }  // namespace
@@ -514,7 +572,7 @@ sdg_status sdg_rk_stage(sdg_ctx* ctx, int stage, const void* dev_Tn, const void*
   if (dev_Tout == dev_Ts || (stage > 0 && dev_Tout == dev_Tn))
     return fail(SDG_E_ARG, "sdg_rk_stage: output must not alias an input");
   DeviceGuard g(ctx->device);
-  st = enqueue_stage(ctx, stage, dev_Tn, dev_Ts, dev_Tout);
+  st = enqueue_stage(ctx, stage, dev_Tn, dev_Ts, dev_Tout, ctx->stream);
   if (st == SDG_OK) g_err.clear();
   return st;
 }
@@ -526,7 +584,7 @@ sdg_status sdg_vertical_implicit_solve(sdg_ctx* ctx, const void* dev_Tstar, void
   if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_vertical_implicit_solve needs sdg_set_diffusivity");
   if (!dev_Tstar || !dev_Tout) return fail(SDG_E_ARG, "sdg_vertical_implicit_solve: NULL buffer");
   DeviceGuard g(ctx->device);
-  sdg_status st = enqueue_solve(ctx, dev_Tstar, dev_Tout);
+  sdg_status st = enqueue_solve(ctx, dev_Tstar, dev_Tout, ctx->stream);
   if (st == SDG_OK) g_err.clear();
   return st;
 }
@@ -539,14 +597,8 @@ sdg_status sdg_step(sdg_ctx* ctx, int n_steps) {
   if (n_steps < 0) return fail(SDG_E_ARG, "n_steps must be >= 0");
   DeviceGuard g(ctx->device);
   void* X = ctx->state;
-  void* A = ctx->stage_a;
-  void* B = ctx->stage_b;
-  for (int n = 0; n < n_steps; ++n) {
-    if ((st = enqueue_stage(ctx, 0, nullptr, X, A)) != SDG_OK) return st;
-    if ((st = enqueue_stage(ctx, 1, X, A, B)) != SDG_OK) return st;
-    if ((st = enqueue_stage(ctx, 2, X, B, A)) != SDG_OK) return st;
-    if ((st = enqueue_solve(ctx, A, X)) != SDG_OK) return st;
-  }
+  for (int n = 0; n < n_steps; ++n)
+    if ((st = enqueue_step(ctx, ctx->stream)) != SDG_OK) return st;
   if (ctx->check_finite && n_steps > 0) {
     hipError_t e = launch_finite_check(ctx->dm, X, ctx->plan.F, ctx->plan.fp32, ctx->flag, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "finite check launch");
@@ -572,6 +624,194 @@ sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass) {
   e = hipMemcpyAsync(host_mass, ctx->msum, sizeof(double) * P.F * P.n_members, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "sdg_mass");
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out) {
+  if (!ctx || !out) return fail(SDG_E_ARG, "sdg_get_tuning: NULL argument");
+  out->tile_layers = kTileLayerOptions[ctx->tile_choice];
+  out->xcd_remap = ctx->xcd;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* t) {
+  if (!ctx || !t) return fail(SDG_E_ARG, "sdg_set_tuning: NULL argument");
+  int choice = -1;
+  for (int i = 0; i < kTileChoices; ++i)
+    if (kTileLayerOptions[i] == t->tile_layers) choice = i;
+  if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2 or 4 (got %d)", t->tile_layers);
+  if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(SDG_E_ARG, "xcd_remap must be 0 or 1");
+  ctx->tile_choice = choice;
+  ctx->xcd = t->xcd_remap;
+  ctx->graph_valid = false;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen) {
+  sdg_status st = check_explicit(ctx, "sdg_autotune");
+  if (st != SDG_OK) return st;
+  if (!ctx->state) return fail(SDG_E_STATE, "sdg_autotune needs sdg_set_fields");
+  if (reps < 1) reps = 1;
+  DeviceGuard g(ctx->device);
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "sdg_autotune: hipEventCreate");
+  float best = 1e30f;
+  int best_choice = ctx->tile_choice, best_xcd = ctx->xcd;
+  for (int c = 0; c < kTileChoices && st == SDG_OK; ++c) {
+    for (int x = 0; x <= 1 && st == SDG_OK; ++x) {
+      ctx->tile_choice = c;
+      ctx->xcd = x;
+      // stage 1 reads both stage inputs: the most demanding launch
+      st = enqueue_stage(ctx, 1, ctx->state, ctx->state, ctx->stage_a, ctx->stream);
+      if (st != SDG_OK) break;
+      e = hipEventRecord(e0, ctx->stream);
+      for (int r = 0; r < reps && st == SDG_OK; ++r)
+        st = enqueue_stage(ctx, 1, ctx->state, ctx->state, ctx->stage_a, ctx->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "sdg_autotune: timing");
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_choice = c;
+        best_xcd = x;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tile_choice = best_choice;
+  ctx->xcd = best_xcd;
+  ctx->graph_valid = false;
+  if (st != SDG_OK) return st;
+  if (chosen) {
+    chosen->tile_layers = kTileLayerOptions[best_choice];
+    chosen->xcd_remap = best_xcd;
+  }
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_graph_capture_step(sdg_ctx* ctx) {
+  sdg_status st = check_explicit(ctx, "sdg_graph_capture_step");
+  if (st != SDG_OK) return st;
+  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_graph_capture_step needs sdg_set_diffusivity");
+  if (!ctx->state) return fail(SDG_E_STATE, "sdg_graph_capture_step needs sdg_set_fields");
+  DeviceGuard g(ctx->device);
+  drop_graph(ctx);
+  hipError_t e = hipSuccess;
+  if (!ctx->cap_stream) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "sdg_graph_capture_step: stream");
+  // the captured kernels must not overtake work already queued on the
+  // context stream: capture starts after it has drained
+  e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "sdg_graph_capture_step: begin capture");
+  st = enqueue_step(ctx, ctx->cap_stream);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(ctx->cap_stream, &graph);
+  if (st != SDG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "sdg_graph_capture_step: end capture");
+  ctx->graph = graph;
+  e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(ctx);
+    return hip_fail(e, "sdg_graph_capture_step: instantiate");
+  }
+  ctx->graph_valid = true;
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_graph_launch(sdg_ctx* ctx, int n_steps) {
+  if (!ctx) return fail(SDG_E_ARG, "context is NULL");
+  if (!ctx->graph_valid) return fail(SDG_E_STATE, "no valid captured step (capture again after any set_* call)");
+  if (n_steps < 0) return fail(SDG_E_ARG, "n_steps must be >= 0");
+  DeviceGuard g(ctx->device);
+  for (int n = 0; n < n_steps; ++n) {
+    hipError_t e = hipGraphLaunch(ctx->graph_exec, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  }
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_apply_mass(sdg_ctx* ctx, const void* dev_X, void* dev_Y, int inverse) {
+  if (!ctx || !dev_X || !dev_Y) return fail(SDG_E_ARG, "sdg_apply_mass: NULL argument");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_apply_mass needs an uploaded mesh");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_mass_apply(ctx->dm, dev_X, dev_Y, ctx->plan.F, ctx->plan.fp32, inverse != 0, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "mass apply launch");
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double* host_out) {
+  if (!ctx || !dev_X || !dev_Y || !host_out) return fail(SDG_E_ARG, "sdg_m_dot: NULL argument");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_m_dot needs an uploaded mesh");
+  DeviceGuard g(ctx->device);
+  const Plan& P = ctx->plan;
+  hipError_t e = launch_mdot_columns(ctx->dm, dev_X, dev_Y, P.F, P.fp32, ctx->colmass, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "m_dot launch");
+  e = launch_member_sum(ctx->colmass, P.CS, P.F, ctx->member_off_dev, P.n_members, ctx->msum, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "m_dot reduction launch");
+  e = hipMemcpyAsync(host_out, ctx->msum, sizeof(double) * P.F * P.n_members, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "sdg_m_dot");
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_next,
+                            double* dev_dkappa) {
+  sdg_status st = check_explicit(ctx, "sdg_step_adjoint");
+  if (st != SDG_OK) return st;
+  if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint needs an FP64 context");
+  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint needs sdg_set_diffusivity");
+  if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint: NULL buffer");
+  if (dev_dkappa && !dev_x_next) return fail(SDG_E_ARG, "sdg_step_adjoint: dkappa needs x_next");
+  if (dev_z_out == ctx->stage_a || dev_z_out == ctx->stage_b || dev_z_next == ctx->stage_a || dev_z_next == ctx->stage_b)
+    return fail(SDG_E_ARG, "sdg_step_adjoint: buffers must not be the workspace stage buffers");
+  DeviceGuard g(ctx->device);
+  const Plan& P = ctx->plan;
+  double* mu = static_cast<double*>(dev_z_out);
+  double* zb2 = static_cast<double*>(ctx->stage_a);
+  double* zb1 = static_cast<double*>(ctx->stage_b);
+  const double* U = static_cast<const double*>(ctx->U);
+  const int tl = kTileLayerOptions[ctx->tile_choice];
+  const WgTile* tiles = ctx->tiles[ctx->tile_choice];
+  const int nt = P.n_tiles[ctx->tile_choice];
+  hipStream_t s = ctx->stream;
+  hipError_t e = launch_tsolve(ctx->dm, P.F, static_cast<const double*>(dev_z_next), mu, ctx->kappa,
+                               ctx->scratch, ctx->dt, ctx->eta, s);
+  if (e != hipSuccess) return hip_fail(e, "transposed solve launch");
+  if (dev_dkappa) {
+    e = launch_kappa_gradient(ctx->dm, P.F, mu, static_cast<const double*>(dev_x_next), ctx->kpart, ctx->eta,
+                              ctx->dt, dev_dkappa, s);
+    if (e != hipSuccess) return hip_fail(e, "kappa gradient launch");
+  }
+  const bool wz = ctx->w_zero;
+  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, mu, nullptr, nullptr, zb2, U, ctx->dt,
+                           2.0 / 3.0, 0.0, 0.0, s);
+  if (e == hipSuccess)
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb2, nullptr, nullptr, zb1, U, ctx->dt,
+                             0.25, 0.0, 0.0, s);
+  if (e == hipSuccess)
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb1, mu, zb2, mu, U, ctx->dt, 1.0,
+                             1.0 / 3.0, 0.75, s);
+  if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
   g_err.clear();
   return SDG_OK;
 }

@@ -47,18 +47,21 @@ struct DevMesh {
   const int32_t* col_member;   // [n_col_slots] member id (-1 on padding)
 };
 
-// A workgroup of the per-prism kernels covers 4 consecutive layers of one
-// cell: (cell, first layer).
+// A workgroup of the per-prism kernels covers tile_layers consecutive layers
+// of one cell: (cell, first layer).
 struct WgTile {
   int32_t cell;
   int32_t layer0;
 };
-constexpr int kTileLayers = 4;
+constexpr int kTileChoices = 3;                 // tile_layers in {1, 2, 4}
+constexpr int kTileLayerOptions[kTileChoices] = {1, 2, 4};
 
 struct StageArgs {
   DevMesh m;
-  const WgTile* tiles;
+  const WgTile* tiles;   // one entry per workgroup: (cell, first layer)
   int32_t n_tiles;
+  int32_t tile_layers;   // layers per workgroup (1, 2 or 4): blockDim = 64 * tile_layers
+  int32_t xcd;           // 1: XCD-contiguous tile order
   int32_t n_fields;
   const void* Tn;      // [F][6][n_slots]
   const void* Ts;
@@ -93,6 +96,20 @@ hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fiel
                              hipStream_t s);
 hipError_t launch_finite_check(const DevMesh& m, const void* T, int n_fields, bool fp32,
                                int32_t* flag, hipStream_t s);
+
+// Adjoint (FP64 only).
+hipError_t launch_adjoint_stage(const DevMesh& m, const WgTile* tiles, int n_tiles, int tile_layers, int xcd,
+                                int n_fields, bool w_zero, const double* Y, const double* X1, const double* X2,
+                                double* out, const double* U, double dt, double b, double a1, double a2,
+                                hipStream_t s);
+hipError_t launch_tsolve(const DevMesh& m, int n_fields, const double* Z, double* mu, const double* kappa,
+                         double* scratch, double dt, double eta, hipStream_t s);
+hipError_t launch_kappa_gradient(const DevMesh& m, int n_fields, const double* mu, const double* x,
+                                 double* partial, double eta, double dt, double* dkappa, hipStream_t s);
+hipError_t launch_mass_apply(const DevMesh& m, const void* X, void* Y, int n_fields, bool fp32, bool inverse,
+                             hipStream_t s);
+hipError_t launch_mdot_columns(const DevMesh& m, const void* X, const void* Y, int n_fields, bool fp32,
+                               double* col_out, hipStream_t s);
 
 // Workgroup index -> tile index so that each of the 8 XCDs (which receive
 // workgroups round-robin) processes one contiguous range of tiles, keeping

@@ -54,6 +54,22 @@ template <typename R> __device__ __forceinline__ const R* zl_of(const DevMesh& m
 template <> __device__ __forceinline__ const double* zl_of<double>(const DevMesh& m) { return m.zl; }
 template <> __device__ __forceinline__ const float* zl_of<float>(const DevMesh& m) { return m.zl32; }
 
+// Load from a row whose base pointer is wavefront-uniform, at a 32-bit byte
+// offset: lets the compiler use the scalar-base + vector-offset load form
+// instead of per-lane 64-bit address arithmetic.
+template <typename T>
+__device__ __forceinline__ T ldb(const T* __restrict__ row, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void stb(T* __restrict__ row, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(row) + byte_off) = v;
+}
+
+// Scheduling fence between phases: keeps the compiler from hoisting every
+// neighbour load of the kernel to its top (which costs occupancy).
+#define SDG_PHASE() __builtin_amdgcn_sched_barrier(0)
+
 template <typename R>
 __device__ __forceinline__ R upos(R x) { return x > R(0) ? x : R(0); }
 template <typename R>
@@ -62,7 +78,7 @@ __device__ __forceinline__ R uneg(R x) { return x < R(0) ? x : R(0); }
 template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   const DevMesh& m = a.m;
-  const WgTile tile = a.tiles[xcd_tile(blockIdx.x, a.n_tiles)];
+  const WgTile tile = a.tiles[a.xcd ? xcd_tile(blockIdx.x, a.n_tiles) : (int)blockIdx.x];
   const int lane = threadIdx.x & (kCell - 1);
   const int l = tile.layer0 + (threadIdx.x >> 6);
   const int c = tile.cell * kCell + lane;
@@ -72,22 +88,26 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   const size_t S = (size_t)m.n_slots;
   const size_t LS = (size_t)m.n_lslots;
   const int CS = m.n_col_slots;
-  const size_t p = (size_t)m.cell_base[tile.cell] + (size_t)l * kCell + lane;
-  const size_t lt = (size_t)m.cell_lbase[tile.cell] + (size_t)l * kCell + lane;
+  const uint32_t p = (uint32_t)m.cell_base[tile.cell] + (uint32_t)l * kCell + lane;
+  const uint32_t lt = (uint32_t)m.cell_lbase[tile.cell] + (uint32_t)l * kCell + lane;
+  const uint32_t rs = (uint32_t)(S * sizeof(R));     // bytes per node row
+  const uint32_t po = p * (uint32_t)sizeof(R);       // this prism's byte offset in a row
+  const uint32_t co = (uint32_t)c * (uint32_t)sizeof(R);
   const R* __restrict__ Ts = static_cast<const R*>(a.Ts);
   const R* __restrict__ U = static_cast<const R*>(a.U);
   const R* __restrict__ geo = geo_of<R>(m);
   const R* __restrict__ zl = zl_of<R>(m);
+  const uint32_t co4 = (uint32_t)c * 4u;
 
-  const R xxi = geo[G_XXI * CS + c], xet = geo[G_XET * CS + c];
-  const R yxi = geo[G_YXI * CS + c], yet = geo[G_YET * CS + c];
-  const R Jh = geo[G_JH * CS + c];
+  const R xxi = ldb(geo + G_XXI * CS, co), xet = ldb(geo + G_XET * CS, co);
+  const R yxi = ldb(geo + G_YXI * CS, co), yet = ldb(geo + G_YET * CS, co);
+  const R Jh = ldb(geo + G_JH * CS, co);
 
   R zt[3], zb[3], dz[3];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    zt[v] = zl[v * LS + lt];
-    zb[v] = zl[v * LS + lt + kCell];
+    zt[v] = ldb(zl + v * LS, lt * (uint32_t)sizeof(R));
+    zb[v] = ldb(zl + v * LS, (lt + kCell) * (uint32_t)sizeof(R));
     dz[v] = zt[v] - zb[v];
   }
 
@@ -95,13 +115,13 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
 #pragma unroll
   for (int f = 0; f < NF; ++f)
 #pragma unroll
-    for (int i = 0; i < 6; ++i) T[f][i] = Ts[(size_t)(f * 6 + i) * S + p];
+    for (int i = 0; i < 6; ++i) T[f][i] = ldb(Ts + (size_t)(f * 6 + i) * S, po);
   R u[6], v[6], w[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    u[i] = U[(size_t)(0 * 6 + i) * S + p];
-    v[i] = U[(size_t)(1 * 6 + i) * S + p];
-    w[i] = WZ ? R(0) : U[(size_t)(2 * 6 + i) * S + p];
+    u[i] = ldb(U + (size_t)(0 * 6 + i) * S, po);
+    v[i] = ldb(U + (size_t)(1 * 6 + i) * S, po);
+    w[i] = WZ ? R(0) : ldb(U + (size_t)(2 * 6 + i) * S, po);
   }
 
   R res[NF][6];
@@ -176,28 +196,32 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   // ---------------- lateral faces ----------------
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
+    SDG_PHASE();
     const int A = e, B = (e + 1) % 3;
-    const int nslot = m.nbr_slot[e * CS + c];
-    const int meta = m.nbr_meta[e * CS + c];
+    const int nslot = ldb(m.nbr_slot + e * CS, co4);
+    const int meta = ldb(m.nbr_meta + e * CS, co4);
     const bool interior = nslot >= 0;
     if (interior && l >= (meta >> 2)) continue;  // shallower neighbour: wall
-    const R nx = geo[(G_NX + e) * CS + c], ny = geo[(G_NY + e) * CS + c];
-    const R Le = geo[(G_LE + e) * CS + c];
+    const R nx = ldb(geo + (G_NX + e) * CS, co), ny = ldb(geo + (G_NY + e) * CS, co);
+    const R Le = ldb(geo + (G_LE + e) * CS, co);
     // normal velocity at the 4 face nodes (A top, B top, A bottom, B bottom)
     R un[4] = {nx * u[A] + ny * v[A], nx * u[B] + ny * v[B], nx * u[A + 3] + ny * v[A + 3],
                nx * u[B + 3] + ny * v[B + 3]};
-    size_t pn = 0;
-    int nA = 0, nB = 0;
+    // byte offsets (within a field block) of the neighbour's 4 face nodes
+    uint32_t no[4] = {0, 0, 0, 0};
     if (interior) {
       const int kp = meta & 3;
-      nA = (kp + 1) % 3;  // neighbour's local vertex that is our vertex A
-      nB = kp;            // ... our vertex B
-      pn = (size_t)nslot + (size_t)l * kCell;
-      const int nodes[4] = {nA, nB, nA + 3, nB + 3};
+      const uint32_t nA = (uint32_t)((kp + 1) % 3);  // neighbour's local vertex that is our vertex A
+      const uint32_t nB = (uint32_t)kp;              // ... our vertex B
+      const uint32_t pno = ((uint32_t)nslot + (uint32_t)l * kCell) * (uint32_t)sizeof(R);
+      no[0] = nA * rs + pno;
+      no[1] = nB * rs + pno;
+      no[2] = no[0] + 3u * rs;
+      no[3] = no[1] + 3u * rs;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const R uo = U[(size_t)(0 * 6 + nodes[j]) * S + pn];
-        const R vo = U[(size_t)(1 * 6 + nodes[j]) * S + pn];
+        const R uo = ldb(U, no[j]);
+        const R vo = ldb(U + 6 * S, no[j]);
         un[j] = R(0.5) * (un[j] + nx * uo + ny * vo);
       }
     }
@@ -218,10 +242,9 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     for (int f = 0; f < NF; ++f) {
       R to[4];
       if (interior) {
-        to[0] = Ts[(size_t)(f * 6 + nA) * S + pn];
-        to[1] = Ts[(size_t)(f * 6 + nB) * S + pn];
-        to[2] = Ts[(size_t)(f * 6 + nA + 3) * S + pn];
-        to[3] = Ts[(size_t)(f * 6 + nB + 3) * S + pn];
+        const R* fb = Ts + (size_t)(f * 6) * S;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) to[j] = ldb(fb, no[j]);
       } else {
         to[0] = to[1] = to[2] = to[3] = R(a.t_ext[f]);
       }
@@ -246,12 +269,13 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   // ---------------- top and bottom faces ----------------
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
+    SDG_PHASE();
     // side 0: top face (nodes 0..2, neighbour above, its bottom nodes);
     // side 1: bottom face (nodes 3..5, neighbour below, its top nodes).
     const int o = side == 0 ? 0 : 3;
     const int oo = side == 0 ? 3 : 0;
     const bool has_nb = side == 0 ? (l > 0) : (l < N - 1);
-    const size_t pn = side == 0 ? p - kCell : p + kCell;
+    const uint32_t pno = (side == 0 ? p - kCell : p + kCell) * (uint32_t)sizeof(R);
     const R* zf = side == 0 ? zt : zb;
     // J_h * grad_h z of the (planar) face
     const R zxi = zf[1] - zf[0], zet = zf[2] - zf[0];
@@ -268,10 +292,10 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     if (has_nb) {
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
-        const R uo = U[(size_t)(0 * 6 + oo + n) * S + pn];
-        const R vo = U[(size_t)(1 * 6 + oo + n) * S + pn];
+        const R uo = ldb(U + (size_t)(0 * 6 + oo + n) * S, pno);
+        const R vo = ldb(U + (size_t)(1 * 6 + oo + n) * S, pno);
         R val = -(uo * jzx + vo * jzy);
-        if (!WZ) val += Jh * U[(size_t)(2 * 6 + oo + n) * S + pn];
+        if (!WZ) val += Jh * ldb(U + (size_t)(2 * 6 + oo + n) * S, pno);
         un[n] = R(0.5) * (un[n] + val);
       }
     }
@@ -287,7 +311,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
       R to[3];
       if (has_nb) {
 #pragma unroll
-        for (int n = 0; n < 3; ++n) to[n] = Ts[(size_t)(f * 6 + oo + n) * S + pn];
+        for (int n = 0; n < 3; ++n) to[n] = ldb(Ts + (size_t)(f * 6 + oo + n) * S, pno);
       } else {
         to[0] = to[1] = to[2] = R(a.t_ext[f]);
       }
@@ -305,6 +329,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   }
 
   // ---------------- M^-1 and the stage combination ----------------
+  SDG_PHASE();
   // Mz = J_h/120 * m, m_aa = 3 dz_a + dz_b + dz_c, m_ab = dz_a + dz_b + dz_c / 2.
   const R m00 = R(3) * dz[0] + dz[1] + dz[2];
   const R m11 = dz[0] + R(3) * dz[1] + dz[2];
@@ -339,22 +364,22 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
     L[5] = sc * (c02 * hb[0] + c12 * hb[1] + c22 * hb[2]);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      const size_t idx = (size_t)(f * 6 + i) * S + p;
+      const size_t row = (size_t)(f * 6 + i) * S;
       R out;
       if (RHS) {
         out = L[i];
       } else {
         out = cb * (T[f][i] + dt * L[i]);
-        if (READ_TN) out += ca * Tn[idx];
+        if (READ_TN) out += ca * ldb(Tn + row, po);
       }
-      Out[idx] = out;
+      stb(Out + row, po, out);
     }
   }
 }
 
 template <typename R, int NF>
 hipError_t launch_nf(const StageArgs& a, bool w_zero, bool rhs_only, bool read_tn, hipStream_t s) {
-  dim3 grid(a.n_tiles), block(256);
+  dim3 grid(a.n_tiles), block(kCell * a.tile_layers);
   if (rhs_only) {
     if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, true, false>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((stage_kernel<R, NF, false, true, false>), grid, block, 0, s, a);

@@ -25,7 +25,8 @@ EXPORTED = (
     "sdg_abi_version", "sdg_last_error", "sdg_query_layout", "sdg_prism_slots", "sdg_create",
     "sdg_destroy", "sdg_mesh_upload", "sdg_set_params", "sdg_set_velocity", "sdg_set_diffusivity",
     "sdg_set_fields", "sdg_rhs_3d", "sdg_rk_stage", "sdg_vertical_implicit_solve", "sdg_step",
-    "sdg_mass", "sdg_sync",
+    "sdg_mass", "sdg_sync", "sdg_get_tuning", "sdg_set_tuning", "sdg_autotune",
+    "sdg_graph_capture_step", "sdg_graph_launch", "sdg_apply_mass", "sdg_m_dot", "sdg_step_adjoint",
 )
 
 
@@ -64,6 +65,10 @@ class Layout(ctypes.Structure):
         ("velocity_bytes", ctypes.c_size_t),
         ("workspace_bytes", ctypes.c_size_t),
     ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_layers", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -107,6 +112,14 @@ def load_library(path: str | None = None):
         "sdg_step": ([vp, i32], i32),
         "sdg_mass": ([vp, vp, vp], i32),
         "sdg_sync": ([vp], i32),
+        "sdg_get_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
+        "sdg_set_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
+        "sdg_autotune": ([vp, i32, ctypes.POINTER(Tuning)], i32),
+        "sdg_graph_capture_step": ([vp], i32),
+        "sdg_graph_launch": ([vp, i32], i32),
+        "sdg_apply_mass": ([vp, vp, vp, i32], i32),
+        "sdg_m_dot": ([vp, vp, vp, vp], i32),
+        "sdg_step_adjoint": ([vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -292,6 +305,54 @@ class SlimDG:
 
     def sync(self):
         _check(self.lib.sdg_sync(self.ctx))
+
+    # -- launch shape, autotuning, graph replay -------------------------------
+    def get_tuning(self) -> tuple[int, int]:
+        t = Tuning()
+        _check(self.lib.sdg_get_tuning(self.ctx, ctypes.byref(t)))
+        return int(t.tile_layers), int(t.xcd_remap)
+
+    def set_tuning(self, tile_layers: int, xcd_remap: int = 1):
+        t = Tuning(int(tile_layers), int(xcd_remap))
+        _check(self.lib.sdg_set_tuning(self.ctx, ctypes.byref(t)))
+
+    def autotune(self, reps: int = 5) -> tuple[int, int]:
+        t = Tuning()
+        _check(self.lib.sdg_autotune(self.ctx, int(reps), ctypes.byref(t)))
+        return int(t.tile_layers), int(t.xcd_remap)
+
+    def graph_capture_step(self):
+        _check(self.lib.sdg_graph_capture_step(self.ctx))
+
+    def graph_launch(self, n_steps: int = 1):
+        _check(self.lib.sdg_graph_launch(self.ctx, int(n_steps)))
+
+    # -- mass operator and adjoint ---------------------------------------------
+    def apply_mass(self, X, out=None, inverse: bool = False):
+        out = self.new_state() if out is None else out
+        self._check_nodal(X, self.n_fields)
+        self._check_nodal(out, self.n_fields)
+        _check(self.lib.sdg_apply_mass(self.ctx, _ptr(X), _ptr(out), int(bool(inverse))))
+        return out
+
+    def m_dot(self, X, Y) -> np.ndarray:
+        """(n_members, n_fields) array of X_f^T M Y_f."""
+        self._check_nodal(X, self.n_fields)
+        self._check_nodal(Y, self.n_fields)
+        out = np.zeros(self.mesh.n_members * self.n_fields, dtype=np.float64)
+        _check(self.lib.sdg_m_dot(self.ctx, _ptr(X), _ptr(Y), out.ctypes.data))
+        return out.reshape(self.mesh.n_members, self.n_fields)
+
+    def step_adjoint(self, z_next, z_out, x_next=None, dkappa=None):
+        self._check_nodal(z_next, self.n_fields)
+        self._check_nodal(z_out, self.n_fields)
+        if x_next is not None:
+            self._check_nodal(x_next, self.n_fields)
+        if dkappa is not None and (dkappa.dtype != self.torch.float64 or dkappa.numel() < int(self.layout.max_layers)):
+            raise ValueError("dkappa must be a float64 device tensor with >= max_layers entries")
+        _check(self.lib.sdg_step_adjoint(self.ctx, _ptr(z_next), _ptr(z_out),
+                                         None if x_next is None else _ptr(x_next),
+                                         None if dkappa is None else _ptr(dkappa)))
 
 
 def from_workload(w, precision: int = SDG_FP64, device: int = 0):
