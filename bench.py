@@ -18,8 +18,10 @@ oracle timed on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +32,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "prism-node DOF updates/sec per RK stage + HBM GB/s (FP32 vs FP64, 1 GPU)"
 HBM_PEAK = 8.0e12  # B/s, MI355X HBM3E
+STAGE_SRC = os.path.join(ROOT, "paper_2605_16082_amd", "csrc", "stage.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernel_fp64_4fields_199712x30_pmc.md")
+
+
+def stage_source_sha256() -> str:
+    return hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per stage launch measured with rocprofv3 (FETCH_SIZE and
+    WRITE_SIZE, scaled by a 1 GiB copy) for the current stage kernel source,
+    or None if the committed counter summary belongs to another version."""
+    try:
+        txt = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    m = re.search(r"stage_source_sha256:\s*([0-9a-f]{64})", txt)
+    t = re.search(r"traffic_bytes_mean_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != stage_source_sha256():
+        return None
+    return float(t.group(1))
 
 
 def log(*a):
@@ -65,6 +88,7 @@ def time_calls(torch, fn, reps):
 
 def run_gpu(w, precision, steps, warmup, torch, P_mod):
     s, U, kappa, state = P_mod.from_workload(w, precision)
+    tuning = s.autotune(reps=3)
     torch.cuda.synchronize()
     P, C, F = w.n_prisms, w.n_cols, w.n_fields
     n_lev = P + C
@@ -96,6 +120,7 @@ def run_gpu(w, precision, steps, warmup, torch, P_mod):
         "stage_bytes_per_launch": [int(b) for b in by],
         "solve_GBps": sb / t_sv / 1e9,
         "solve_bytes_per_launch": int(sb),
+        "tuning": {"tile_layers": tuning[0], "xcd_remap": tuning[1]},
     }
     del s, U, kappa, state, A, B
     torch.cuda.empty_cache()
@@ -151,6 +176,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--n", type=int, default=316, help="split squares per side (316: 199,712 triangles)")
     ap.add_argument("--layers", type=int, default=30)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device twice (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU column "
@@ -164,6 +191,13 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     P_mod.load_library()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+            torch.cuda.synchronize()
+        del src, dst
     t0 = time.perf_counter()
     w = W.config2(n=args.n, n_layers=args.layers)
     log(f"workload built in {time.perf_counter() - t0:.1f} s: {w.n_cols} columns, {w.n_prisms} prisms, "
@@ -206,12 +240,15 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": r64["stage_GBps"] * 1e9 / HBM_PEAK,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "bytes per launch (mean of the 3 stage launches)",
+            "algorithmic_bytes_mean_per_launch": sum(r64["stage_bytes_per_launch"]) / 3,
         },
         "kernels_fp64": {
             "t_stage_s": r64["t_stage"], "t_solve_s": r64["t_solve"],
             "stage_rate": r64["stage_rate"], "solve_GBps": r64["solve_GBps"],
             "stage_bytes_per_launch": r64["stage_bytes_per_launch"],
+            "tuning": r64["tuning"],
             "solve_bytes_per_launch": r64["solve_bytes_per_launch"],
         },
         "cpu_baseline": cpu,
@@ -223,6 +260,7 @@ def main():
             "t_stage_s": r32["t_stage"], "t_solve_s": r32["t_solve"],
             "stage_rate": r32["stage_rate"], "stage_GBps": r32["stage_GBps"],
             "stage_frac": r32["stage_GBps"] * 1e9 / HBM_PEAK, "solve_GBps": r32["solve_GBps"],
+            "tuning": r32["tuning"],
         }
     print(json.dumps(out), flush=True)
 

@@ -187,7 +187,7 @@ sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
 sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
 /* Launch shape of the fused stage kernel.  Results do not depend on it.
- * tile_layers: layers per workgroup of 64 columns (1, 2 or 4; default 4);
+ * tile_layers: layers per workgroup of 64 columns (1, 2 or 4; default 2);
  * xcd_remap: 1 = give each XCD one contiguous range of cells (default). */
 typedef struct {
   int32_t tile_layers;

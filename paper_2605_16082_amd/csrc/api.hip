@@ -220,7 +220,7 @@ struct sdg_ctx {
   char* ws = nullptr;
   WgTile* tiles[kTileChoices] = {nullptr, nullptr, nullptr};
   // launch shape of the stage kernel (chosen by sdg_set_tuning / sdg_autotune)
-  int tile_choice = 2;   // index into kTileLayerOptions (4 layers)
+  int tile_choice = 1;   // index into kTileLayerOptions (2 layers)
   int xcd = 1;
   // captured step
   hipStream_t cap_stream = nullptr;

@@ -1,9 +1,13 @@
 // Explicit DG operator and SSP-RK3 stage on extruded linear prisms.
 //
-// One thread per prism.  A workgroup of 256 threads covers 4 consecutive
-// layers of one cell of 64 columns, so each wavefront reads 64 consecutive
-// slots of every nodal array (cell layout, section 2.1.1 of the paper, with
-// wavefront-sized cells).  Per prism and field it computes
+// One thread per prism.  A workgroup covers 1, 2 or 4 consecutive layers of
+// one cell of 64 columns (one wavefront per layer), so each wavefront reads 64
+// consecutive slots of every nodal array (cell layout, section 2.1.1 of the
+// paper, with wavefront-sized cells).  No load depends on control flow: lanes
+// past their column's depth compute on in-bounds padding slots and skip the
+// store, and faces without a neighbour address the prism's own nodes and
+// select the exterior value, so each wavefront needs only two dependent
+// memory round trips (own data and neighbour slots, then neighbour data).  Per prism and field it computes
 //
 //   R_i = int_K T U.grad(phi_i) dV - sum_faces int_f phi_i Fhat dS
 //   L   = M^-1 R                          (block-diagonal mass matrix)
@@ -66,9 +70,6 @@ __device__ __forceinline__ void stb(T* __restrict__ row, uint32_t byte_off, T v)
   *reinterpret_cast<T*>(reinterpret_cast<char*>(row) + byte_off) = v;
 }
 
-// Scheduling fence between phases: keeps the compiler from hoisting every
-// neighbour load of the kernel to its top (which costs occupancy).
-#define SDG_PHASE() __builtin_amdgcn_sched_barrier(0)
 
 template <typename R>
 __device__ __forceinline__ R upos(R x) { return x > R(0) ? x : R(0); }
@@ -82,8 +83,12 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   const int lane = threadIdx.x & (kCell - 1);
   const int l = tile.layer0 + (threadIdx.x >> 6);
   const int c = tile.cell * kCell + lane;
+  // Threads past their column's depth still run (on in-bounds padding slots
+  // of their cell) so that no load waits on nlay; only the store is masked.
   const int N = m.nlay[c];
-  if (l >= N) return;
+  const int depth = (m.cell_base[tile.cell + 1] - m.cell_base[tile.cell]) / kCell;
+  if (l >= depth) return;  // uniform per wavefront
+  const bool active = l < N;
 
   const size_t S = (size_t)m.n_slots;
   const size_t LS = (size_t)m.n_lslots;
@@ -196,40 +201,48 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   // ---------------- lateral faces ----------------
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    SDG_PHASE();
     const int A = e, B = (e + 1) % 3;
     const int nslot = ldb(m.nbr_slot + e * CS, co4);
     const int meta = ldb(m.nbr_meta + e * CS, co4);
     const bool interior = nslot >= 0;
-    if (interior && l >= (meta >> 2)) continue;  // shallower neighbour: wall
+    const bool wall = interior && l >= (meta >> 2);   // shallower neighbour: no flux
+    const bool live = interior && !wall;
     const R nx = ldb(geo + (G_NX + e) * CS, co), ny = ldb(geo + (G_NY + e) * CS, co);
     const R Le = ldb(geo + (G_LE + e) * CS, co);
     // normal velocity at the 4 face nodes (A top, B top, A bottom, B bottom)
     R un[4] = {nx * u[A] + ny * v[A], nx * u[B] + ny * v[B], nx * u[A + 3] + ny * v[A + 3],
                nx * u[B + 3] + ny * v[B + 3]};
-    // byte offsets (within a field block) of the neighbour's 4 face nodes
-    uint32_t no[4] = {0, 0, 0, 0};
-    if (interior) {
+    // byte offsets (within a field block) of the neighbour's 4 face nodes;
+    // without a live neighbour they point at this prism's own nodes (never
+    // used, but always in bounds) so the loads need no branch
+    uint32_t no[4];
+    {
       const int kp = meta & 3;
-      const uint32_t nA = (uint32_t)((kp + 1) % 3);  // neighbour's local vertex that is our vertex A
-      const uint32_t nB = (uint32_t)kp;              // ... our vertex B
-      const uint32_t pno = ((uint32_t)nslot + (uint32_t)l * kCell) * (uint32_t)sizeof(R);
+      const uint32_t nA = live ? (uint32_t)((kp + 1) % 3) : (uint32_t)A;
+      const uint32_t nB = live ? (uint32_t)kp : (uint32_t)B;
+      const uint32_t pno = live ? ((uint32_t)nslot + (uint32_t)l * kCell) * (uint32_t)sizeof(R) : po;
       no[0] = nA * rs + pno;
       no[1] = nB * rs + pno;
       no[2] = no[0] + 3u * rs;
       no[3] = no[1] + 3u * rs;
+    }
+    {
+      const int nodes_in[4] = {A, B, A + 3, B + 3};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const R uo = ldb(U, no[j]);
         const R vo = ldb(U + 6 * S, no[j]);
-        un[j] = R(0.5) * (un[j] + nx * uo + ny * vo);
+        const R avg = R(0.5) * (un[j] + nx * uo + ny * vo);
+        un[j] = live ? avg : un[j];
+        (void)nodes_in;
       }
     }
+    const R fscale = wall ? R(0) : R(1);
     R up[3][2], um[3][2];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       const R s = R(kS[j]), s1 = R(1) - R(kS[j]);
-      const R dS = R(kSw[j]) * Le * R(0.5) * (s1 * dz[A] + s * dz[B]);
+      const R dS = fscale * R(kSw[j]) * Le * R(0.5) * (s1 * dz[A] + s * dz[B]);
 #pragma unroll
       for (int k = 0; k < 2; ++k) {
         const R tk = R(kZt[k]), bk = R(kZb[k]);
@@ -241,12 +254,14 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       R to[4];
-      if (interior) {
+      {
         const R* fb = Ts + (size_t)(f * 6) * S;
+        const R te = R(a.t_ext[f]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) to[j] = ldb(fb, no[j]);
-      } else {
-        to[0] = to[1] = to[2] = to[3] = R(a.t_ext[f]);
+        for (int j = 0; j < 4; ++j) {
+          const R x = ldb(fb, no[j]);
+          to[j] = interior ? x : te;
+        }
       }
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -269,13 +284,15 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   // ---------------- top and bottom faces ----------------
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    SDG_PHASE();
     // side 0: top face (nodes 0..2, neighbour above, its bottom nodes);
     // side 1: bottom face (nodes 3..5, neighbour below, its top nodes).
     const int o = side == 0 ? 0 : 3;
     const int oo = side == 0 ? 3 : 0;
     const bool has_nb = side == 0 ? (l > 0) : (l < N - 1);
-    const uint32_t pno = (side == 0 ? p - kCell : p + kCell) * (uint32_t)sizeof(R);
+    // the address only needs the (wavefront-uniform) cell depth; the value
+    // select uses the column's own depth
+    const bool nb_slot = side == 0 ? (l > 0) : (l + 1 < depth);
+    const uint32_t pno = nb_slot ? (side == 0 ? p - kCell : p + kCell) * (uint32_t)sizeof(R) : po;
     const R* zf = side == 0 ? zt : zb;
     // J_h * grad_h z of the (planar) face
     const R zxi = zf[1] - zf[0], zet = zf[2] - zf[0];
@@ -289,15 +306,13 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
       if (!WZ) val += Jh * w[o + n];
       un[n] = val;
     }
-    if (has_nb) {
 #pragma unroll
-      for (int n = 0; n < 3; ++n) {
-        const R uo = ldb(U + (size_t)(0 * 6 + oo + n) * S, pno);
-        const R vo = ldb(U + (size_t)(1 * 6 + oo + n) * S, pno);
-        R val = -(uo * jzx + vo * jzy);
-        if (!WZ) val += Jh * ldb(U + (size_t)(2 * 6 + oo + n) * S, pno);
-        un[n] = R(0.5) * (un[n] + val);
-      }
+    for (int n = 0; n < 3; ++n) {
+      const R uo = ldb(U + (size_t)(0 * 6 + oo + n) * S, pno);
+      const R vo = ldb(U + (size_t)(1 * 6 + oo + n) * S, pno);
+      R val = -(uo * jzx + vo * jzy);
+      if (!WZ) val += Jh * ldb(U + (size_t)(2 * 6 + oo + n) * S, pno);
+      un[n] = has_nb ? R(0.5) * (un[n] + val) : un[n];
     }
     R up[6], um[6];
 #pragma unroll
@@ -309,11 +324,13 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       R to[3];
-      if (has_nb) {
+      {
+        const R te = R(a.t_ext[f]);
 #pragma unroll
-        for (int n = 0; n < 3; ++n) to[n] = ldb(Ts + (size_t)(f * 6 + oo + n) * S, pno);
-      } else {
-        to[0] = to[1] = to[2] = R(a.t_ext[f]);
+        for (int n = 0; n < 3; ++n) {
+          const R x = ldb(Ts + (size_t)(f * 6 + oo + n) * S, pno);
+          to[n] = has_nb ? x : te;
+        }
       }
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
@@ -329,7 +346,6 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   }
 
   // ---------------- M^-1 and the stage combination ----------------
-  SDG_PHASE();
   // Mz = J_h/120 * m, m_aa = 3 dz_a + dz_b + dz_c, m_ab = dz_a + dz_b + dz_c / 2.
   const R m00 = R(3) * dz[0] + dz[1] + dz[2];
   const R m11 = dz[0] + R(3) * dz[1] + dz[2];
@@ -372,7 +388,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
         out = cb * (T[f][i] + dt * L[i]);
         if (READ_TN) out += ca * ldb(Tn + row, po);
       }
-      stb(Out + row, po, out);
+      if (active) stb(Out + row, po, out);
     }
   }
 }
