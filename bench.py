@@ -40,19 +40,22 @@ def stage_source_sha256() -> str:
     return hashlib.sha256(open(STAGE_SRC, "rb").read()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per stage launch measured with rocprofv3 (FETCH_SIZE and
-    WRITE_SIZE, scaled by a 1 GiB copy) for the current stage kernel source,
-    or None if the committed counter summary belongs to another version."""
+def measured_traffic(tuning):
+    """HBM bytes per stage launch (mean of the three stages) measured with
+    rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy, for the
+    current stage kernel source and the given launch shape; None if the
+    committed counter summary belongs to another kernel version."""
     try:
         txt = open(PMC_SUMMARY).read()
     except OSError:
         return None
     m = re.search(r"stage_source_sha256:\s*([0-9a-f]{64})", txt)
-    t = re.search(r"traffic_bytes_mean_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != stage_source_sha256():
+    if not m or m.group(1) != stage_source_sha256():
         return None
-    return float(t.group(1))
+    pat = (r"traffic_bytes_mean_per_launch\[tile_layers=%d xcd_remap=%d persistent=%d\]:\s*([0-9.eE+]+)"
+           % (tuning["tile_layers"], tuning["xcd_remap"], tuning["persistent"]))
+    t = re.search(pat, txt)
+    return float(t.group(1)) if t else None
 
 
 def log(*a):
@@ -120,11 +123,142 @@ def run_gpu(w, precision, steps, warmup, torch, P_mod):
         "stage_bytes_per_launch": [int(b) for b in by],
         "solve_GBps": sb / t_sv / 1e9,
         "solve_bytes_per_launch": int(sb),
-        "tuning": {"tile_layers": tuning[0], "xcd_remap": tuning[1]},
+        "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning)),
     }
     del s, U, kappa, state, A, B
     torch.cuda.empty_cache()
     return res
+
+
+def event_time(torch, fn):
+    """Seconds taken by fn() on the current stream, HIP events around it."""
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def unit_mass(s):
+    """Per member, the mass of T = 1 (the volume), shape (members, 1)."""
+    one = s.new_state()
+    one[:, :, s.slots] = 1.0
+    return s.mass(one)[:, :1]
+
+
+def mass_errors(torch, m, m_ref, ref, vol):
+    """Per member and field: |m - m_ref| / (max |ref_f| * volume), a mass
+    error that stays meaningful for fields whose total is near zero."""
+    scale = ref.abs().amax(dim=(1, 2)).cpu().numpy()[None, :] * vol
+    return np.abs(m - m_ref) / scale
+
+
+def field_errors(torch, x, ref):
+    """Per field: max |x - ref| / max |ref| over all slots (padding is zero in both)."""
+    d = (x.double() - ref).abs().amax(dim=(1, 2))
+    return (d / ref.abs().amax(dim=(1, 2))).tolist()
+
+
+def precision_forms(w, steps, torch, P_mod):
+    """The precision forms after `steps` steps from the same initial state:
+    per-field max-norm error against the FP64 path (which matches the FP64
+    oracle to 1e-12 stage by stage and solve by solve), the difference of
+    each field's total mass over (max |T_f| * volume), and the time per step."""
+    s, U, kappa, x = P_mod.from_workload(w, P_mod.SDG_FP64)
+    s.step(1)
+    s.set_fields(x.copy_(s.scatter(w.T0)))
+    t = event_time(torch, lambda: s.step(steps))
+    ref = x.clone()
+    m_ref = s.mass(ref)
+    vol = unit_mass(s)
+    out = {"steps": steps, "fp64": {"ms_per_step": t / steps * 1e3}}
+    del s, U, kappa, x
+    for key, prec in (("fp32_state_fp64_solve", P_mod.SDG_FP32_STATE_FP64_SOLVE),
+                      ("fp32_everywhere", P_mod.SDG_FP32)):
+        s, U, kappa, x = P_mod.from_workload(w, prec)
+        s.step(1)
+        s.set_fields(x.copy_(s.scatter(w.T0)))
+        t = event_time(torch, lambda: s.step(steps))
+        out[key] = {
+            "ms_per_step": t / steps * 1e3,
+            "max_rel_err_per_field": field_errors(torch, x, ref),
+            "mass_err_per_field": mass_errors(torch, s.mass(x), m_ref, ref, vol)[0].tolist(),
+        }
+        del s, U, kappa, x
+    del ref
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_form(torch, P_mod, W, steps, warmup):
+    """16 z-level members with 5-60 layers per column in one context: the
+    autotuned, graph-captured step in the FP32-state/FP64-solve form against
+    the FP64 path on the same members, with the per-field error between them
+    after warmup + steps steps."""
+    t0 = time.perf_counter()
+    w = W.config4()
+    log(f"batched workload built in {time.perf_counter() - t0:.1f} s: {w.n_cols} columns, "
+        f"{w.n_prisms} prisms, layers {int(w.nlayers.min())}-{int(w.nlayers.max())}")
+    P, F = w.n_prisms, w.n_fields
+    out = {"workload": f"16 members, {w.n_cols} columns, {P} prisms, z-level 5 m layers "
+                       f"({int(w.nlayers.min())}-{int(w.nlayers.max())} per column), 4 fields",
+           "members": int(len(w.member_tri_off) - 1), "prisms": P, "steps": steps, "warmup": warmup}
+    ref = m_ref = None
+    for key, prec in (("fp64", P_mod.SDG_FP64), ("fp32_state_fp64_solve", P_mod.SDG_FP32_STATE_FP64_SOLVE)):
+        s, U, kappa, x = P_mod.from_workload(w, prec)
+        tuning = s.autotune(reps=2)
+        s.graph_capture_step()
+        s.graph_launch(warmup)
+        t = event_time(torch, lambda: s.graph_launch(steps)) / steps
+        r = {"ms_per_step": t * 1e3, "value": 18 * P * F / t,
+             "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))}
+        m = s.mass(x)
+        if ref is None:
+            ref, m_ref, vol = x, m, unit_mass(s)
+        else:
+            r["max_rel_err_per_field_vs_fp64"] = field_errors(torch, x, ref)
+            r["max_member_mass_err_per_field"] = mass_errors(torch, m, m_ref, ref, vol).max(axis=0).tolist()
+            r["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / r["ms_per_step"]
+        out[key] = r
+        log("batched", key, json.dumps(r))
+        del s, U, kappa
+        if key != "fp64":
+            del x
+    del ref, w
+    torch.cuda.empty_cache()
+    return out
+
+
+def adjoint_form(torch, P_mod, W, n_steps=200, every=20):
+    """Gradient of J = sqrt(x_N^T M x_N) with respect to the initial field and
+    the per-layer diffusivity through the hand-written adjoint, with a
+    checkpoint every `every` steps, against the plain forward run."""
+    w = W.config5()
+    s, U, kappa, x = P_mod.from_workload(w)
+    s.step(2)
+    s.set_fields(x.copy_(s.scatter(w.T0)))
+    t_fwd = event_time(torch, lambda: s.step(n_steps))
+    T0 = s.scatter(w.T0).requires_grad_(True)
+    kap = torch.as_tensor(w.kappa, dtype=torch.float64, device=s.device).requires_grad_(True)
+
+    def grad():
+        J = P_mod.MNorm.apply(P_mod.TracerSteps.apply(T0, kap, s, n_steps, every), s)
+        J.backward()
+
+    t_grad = event_time(torch, grad)
+    z = s.new_state()
+    reps = 20
+    t_adj = time_calls(torch, lambda: s.step_adjoint(z, z, x, kap.grad), reps)
+    t_step = time_calls(torch, lambda: s.step(1), reps)
+    out = {"workload": f"{w.n_cols} jittered triangles x 20 sigma layers ({w.n_prisms} prisms), 1 field, FP64",
+           "steps": n_steps, "checkpoint_every": every,
+           "t_forward_s": t_fwd, "t_gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
+           "ms_per_adjoint_step": t_adj * 1e3, "ms_per_forward_step": t_step * 1e3}
+    del s, U, kappa, x, T0, kap, z
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(w, budget_s=20.0):
@@ -176,6 +310,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--n", type=int, default=316, help="split squares per side (316: 199,712 triangles)")
     ap.add_argument("--layers", type=int, default=30)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the precision-form, batched and adjoint measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device twice (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -208,6 +344,12 @@ def main():
     if not args.no_fp32:
         r32 = run_gpu(w, P_mod.SDG_FP32_STATE_FP64_SOLVE, args.steps, args.warmup, torch, P_mod)
         log("fp32 state / fp64 solve", json.dumps(r32))
+    forms = batched = adjoint = None
+    if not args.no_extra:
+        forms = precision_forms(w, 100, torch, P_mod)
+        log("precision forms", json.dumps(forms))
+        adjoint = adjoint_form(torch, P_mod, W)
+        log("adjoint", json.dumps(adjoint))
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w)
@@ -240,7 +382,7 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": r64["stage_GBps"] * 1e9 / HBM_PEAK,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(r64["tuning"]),
             "traffic_unit": "bytes per launch (mean of the 3 stage launches)",
             "algorithmic_bytes_mean_per_launch": sum(r64["stage_bytes_per_launch"]) / 3,
         },
@@ -262,6 +404,13 @@ def main():
             "stage_frac": r32["stage_GBps"] * 1e9 / HBM_PEAK, "solve_GBps": r32["solve_GBps"],
             "tuning": r32["tuning"],
         }
+    if forms is not None:
+        out["precision_forms_after_100_steps"] = forms
+    if not args.no_extra:
+        del w
+        batched = batched_form(torch, P_mod, W, steps=47, warmup=3)
+        out["batched_form"] = batched
+        out["adjoint_form"] = adjoint
     print(json.dumps(out), flush=True)
 
 

@@ -52,11 +52,13 @@
  * sdg_sync or sdg_mass.  No C++ exception crosses the ABI.  A context is used
  * by one host thread at a time.
  *
- * Precision: SDG_FP64 -- state, velocity and fluxes in double; SDG_FP32 --
- * state, velocity, geometry and fluxes in float, vertical solve in FP64;
- * SDG_FP32_STATE_FP64_SOLVE is the same as SDG_FP32 (named for the precision
- * form: FP32 state and fluxes, FP64 column solve and mass sums).  kappa and
- * the mass sums are always double.
+ * Precision (the paper's section 4.1 weighs FP64 against FP32 throughput):
+ *   SDG_FP64                  state, velocity, geometry, fluxes and the
+ *                             column solve in double;
+ *   SDG_FP32_STATE_FP64_SOLVE state, velocity, geometry and fluxes in float,
+ *                             the column solve in double (the precision form);
+ *   SDG_FP32                  everything in float, the column solve included.
+ * kappa, dt and the mass sums are double in every form.
  */
 #ifndef SLIMDG_H
 #define SLIMDG_H
@@ -68,7 +70,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 1
+#define SDG_ABI_VERSION 2
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -186,20 +188,28 @@ sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
  * Synchronises the stream. */
 sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
-/* Launch shape of the fused stage kernel.  Results do not depend on it.
+/* Launch shape of the fused stage kernel (the paper's section 4.1 shows
+ * throughput depending on the column block shape; here the library measures
+ * it).  Results do not depend on it.
  * tile_layers: layers per workgroup of 64 columns (1, 2 or 4; default 2);
- * xcd_remap: 1 = give each XCD one contiguous range of cells (default). */
+ * xcd_remap: 1 = give each XCD one contiguous range of tiles (default);
+ * persistent: 1 = launch only as many workgroups as the device holds at once,
+ *   each walking tiles with a stride (default 0: one workgroup per tile).
+ * The adjoint stages use tile_layers and xcd_remap and ignore persistent. */
 typedef struct {
   int32_t tile_layers;
   int32_t xcd_remap;
+  int32_t persistent;
 } sdg_tuning;
 
 sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out);
 sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* tuning);
 
-/* Time every stage-kernel launch shape (reps launches of stage 1 each, on the
- * set fields and velocity, writing a workspace stage buffer) and keep the
- * fastest.  Synchronises the stream.  `chosen` may be NULL. */
+/* Time every stage-kernel launch shape (3 tile heights x XCD remap off/on x
+ * persistent off/on), each over reps repetitions of the three stages of a
+ * step on the set fields and velocity (the fields are only read; the stages
+ * write the workspace stage buffers), and keep the fastest.  Synchronises
+ * the stream.  `chosen` may be NULL. */
 sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen);
 
 /* Capture one sdg_step (three stages and the column solve, on the set fields)

@@ -222,6 +222,8 @@ struct sdg_ctx {
   // launch shape of the stage kernel (chosen by sdg_set_tuning / sdg_autotune)
   int tile_choice = 1;   // index into kTileLayerOptions (2 layers)
   int xcd = 1;
+  int persistent = 0;
+  int n_cu = 1;          // compute units of the device
   // captured step
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -294,6 +296,12 @@ sdg_status sdg_create(sdg_ctx** out, int device, void* hip_stream) {
   if (!c) return fail(SDG_E_ARG, "out of host memory");
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipDeviceGetAttribute(multiprocessor count)");
+  }
+  if (c->n_cu < 1) c->n_cu = 1;
   *out = c;
   g_err.clear();
   return SDG_OK;
@@ -499,6 +507,8 @@ StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, d
   s.n_tiles = ctx->plan.n_tiles[ctx->tile_choice];
   s.tile_layers = kTileLayerOptions[ctx->tile_choice];
   s.xcd = ctx->xcd;
+  s.persistent = ctx->persistent;
+  s.n_cu = ctx->n_cu;
   s.n_fields = ctx->plan.F;
   s.Tn = Tn;
   s.Ts = Ts;
@@ -531,7 +541,7 @@ sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, hipStream_
   a.scratch = ctx->scratch;
   a.dt = ctx->dt;
   a.eta = ctx->eta;
-  hipError_t e = launch_vsolve(a, ctx->plan.fp32, strm);
+  hipError_t e = launch_vsolve(a, ctx->plan.fp32, ctx->plan.prec == SDG_FP32, strm);
   if (e != hipSuccess) return hip_fail(e, "vertical solve launch");
   return SDG_OK;
 }
@@ -632,6 +642,7 @@ sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out) {
   if (!ctx || !out) return fail(SDG_E_ARG, "sdg_get_tuning: NULL argument");
   out->tile_layers = kTileLayerOptions[ctx->tile_choice];
   out->xcd_remap = ctx->xcd;
+  out->persistent = ctx->persistent;
   g_err.clear();
   return SDG_OK;
 }
@@ -643,12 +654,23 @@ sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* t) {
     if (kTileLayerOptions[i] == t->tile_layers) choice = i;
   if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2 or 4 (got %d)", t->tile_layers);
   if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(SDG_E_ARG, "xcd_remap must be 0 or 1");
+  if (t->persistent != 0 && t->persistent != 1) return fail(SDG_E_ARG, "persistent must be 0 or 1");
   ctx->tile_choice = choice;
   ctx->xcd = t->xcd_remap;
+  ctx->persistent = t->persistent;
   ctx->graph_valid = false;
   g_err.clear();
   return SDG_OK;
 }
+
+namespace {
+sdg_status timed_stages(sdg_ctx* ctx) {
+  sdg_status st = enqueue_stage(ctx, 0, nullptr, ctx->state, ctx->stage_a, ctx->stream);
+  if (st == SDG_OK) st = enqueue_stage(ctx, 1, ctx->state, ctx->stage_a, ctx->stage_b, ctx->stream);
+  if (st == SDG_OK) st = enqueue_stage(ctx, 2, ctx->state, ctx->stage_b, ctx->stage_a, ctx->stream);
+  return st;
+}
+}  // namespace
 
 sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen) {
   sdg_status st = check_explicit(ctx, "sdg_autotune");
@@ -661,17 +683,20 @@ sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen) {
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) return hip_fail(e, "sdg_autotune: hipEventCreate");
   float best = 1e30f;
-  int best_choice = ctx->tile_choice, best_xcd = ctx->xcd;
-  for (int c = 0; c < kTileChoices && st == SDG_OK; ++c) {
-    for (int x = 0; x <= 1 && st == SDG_OK; ++x) {
+  int best_choice = ctx->tile_choice, best_xcd = ctx->xcd, best_pers = ctx->persistent;
+  for (int shape = 0; shape < kTileChoices * 4 && st == SDG_OK; ++shape) {
+    {
+      const int c = shape >> 2, x = shape & 1, pers = (shape >> 1) & 1;
       ctx->tile_choice = c;
       ctx->xcd = x;
-      // stage 1 reads both stage inputs: the most demanding launch
-      st = enqueue_stage(ctx, 1, ctx->state, ctx->state, ctx->stage_a, ctx->stream);
+      ctx->persistent = pers;
+      // the three stages of a step with sdg_step's buffer pattern (Tn = the
+      // fields, stage inputs and outputs in the two workspace buffers), so
+      // the set fields are only read
+      st = timed_stages(ctx);
       if (st != SDG_OK) break;
       e = hipEventRecord(e0, ctx->stream);
-      for (int r = 0; r < reps && st == SDG_OK; ++r)
-        st = enqueue_stage(ctx, 1, ctx->state, ctx->state, ctx->stage_a, ctx->stream);
+      for (int r = 0; r < reps && st == SDG_OK; ++r) st = timed_stages(ctx);
       if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       float ms = 0.f;
@@ -684,6 +709,7 @@ sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen) {
         best = ms;
         best_choice = c;
         best_xcd = x;
+        best_pers = pers;
       }
     }
   }
@@ -691,11 +717,13 @@ sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen) {
   (void)hipEventDestroy(e1);
   ctx->tile_choice = best_choice;
   ctx->xcd = best_xcd;
+  ctx->persistent = best_pers;
   ctx->graph_valid = false;
   if (st != SDG_OK) return st;
   if (chosen) {
     chosen->tile_layers = kTileLayerOptions[best_choice];
     chosen->xcd_remap = best_xcd;
+    chosen->persistent = best_pers;
   }
   g_err.clear();
   return SDG_OK;

@@ -62,6 +62,8 @@ struct StageArgs {
   int32_t n_tiles;
   int32_t tile_layers;   // layers per workgroup (1, 2 or 4): blockDim = 64 * tile_layers
   int32_t xcd;           // 1: XCD-contiguous tile order
+  int32_t persistent;    // 1: grid of resident workgroups walking the tiles
+  int32_t n_cu;          // compute units of the device (persistent grid size)
   int32_t n_fields;
   const void* Tn;      // [F][6][n_slots]
   const void* Ts;
@@ -78,7 +80,7 @@ struct SolveArgs {
   const void* Tstar;
   void* Tout;
   const double* kappa;   // [max_layers]
-  double* scratch;       // [18 + 6F][n_slots] doubles
+  double* scratch;       // [18 + 6F][n_slots] values of the solve's arithmetic type
   double dt;
   double eta;
 };
@@ -88,7 +90,7 @@ hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStrea
 hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,
                         bool read_tn, hipStream_t s);
-hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, hipStream_t s);
+hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, hipStream_t s);
 hipError_t launch_column_mass(const DevMesh& m, const void* T, int n_fields, bool fp32,
                               double* col_mass, hipStream_t s);
 hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fields,

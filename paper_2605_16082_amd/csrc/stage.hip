@@ -27,6 +27,8 @@
 // is H (x) Mz with H = [2 1; 1 2]/3 and Mz_ab = J_h int lambda_a lambda_b
 // z_zeta, so M^-1 = [2 -1; -1 2] (x) Mz^-1 and only a symmetric 3x3 inverse
 // is needed.
+#include <atomic>
+
 #include "internal.h"
 
 namespace sdg {
@@ -77,9 +79,8 @@ template <typename R>
 __device__ __forceinline__ R uneg(R x) { return x < R(0) ? x : R(0); }
 
 template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+__device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile) {
   const DevMesh& m = a.m;
-  const WgTile tile = a.tiles[a.xcd ? xcd_tile(blockIdx.x, a.n_tiles) : (int)blockIdx.x];
   const int lane = threadIdx.x & (kCell - 1);
   const int l = tile.layer0 + (threadIdx.x >> 6);
   const int c = tile.cell * kCell + lane;
@@ -393,20 +394,73 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   }
 }
 
+// One workgroup per tile, or (a.persistent) a grid sized to what the chip
+// holds at once, each workgroup walking tiles with a stride.  With the XCD
+// remap, tile ranges are split into 8 contiguous parts and workgroup b, which
+// the dispatcher places on XCD b mod 8, walks part b mod 8, so the tiles that
+// share faces are processed on one XCD and its L2 (the grid is a multiple of 8).
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
+  const int b = (int)blockIdx.x;
+  int t, end, step;
+  if (!a.persistent) {
+    t = a.xcd ? xcd_tile(b, a.n_tiles) : b;
+    end = t + 1;
+    step = 1;
+  } else if (a.xcd) {
+    const int q = a.n_tiles >> 3, r = a.n_tiles & 7, x = b & 7;
+    const int lo = x * q + (x < r ? x : r);
+    t = lo + (b >> 3);
+    end = lo + q + (x < r ? 1 : 0);
+    step = (int)gridDim.x >> 3;
+  } else {
+    t = b;
+    end = a.n_tiles;
+    step = (int)gridDim.x;
+  }
+  for (; t < end; t += step) stage_tile<R, NF, WZ, RHS, READ_TN>(a, a.tiles[t]);
+}
+
+// Workgroups of `threads` threads that fit on one CU at once, per kernel
+// instance and tile height, queried once.
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+hipError_t resident_per_cu(int threads, int* out) {
+  static std::atomic<int> cache[5];
+  const int k = threads / kCell;
+  int v = cache[k].load(std::memory_order_relaxed);
+  if (v == 0) {
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &v, reinterpret_cast<const void*>(&stage_kernel<R, NF, WZ, RHS, READ_TN>), threads, 0);
+    if (e != hipSuccess) return e;
+    if (v < 1) v = 1;
+    cache[k].store(v, std::memory_order_relaxed);
+  }
+  *out = v;
+  return hipSuccess;
+}
+
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+hipError_t launch_mode(const StageArgs& a, hipStream_t s) {
+  const int threads = kCell * a.tile_layers;
+  int grid = a.n_tiles;
+  if (a.persistent) {
+    int per_cu = 1;
+    hipError_t e = resident_per_cu<R, NF, WZ, RHS, READ_TN>(threads, &per_cu);
+    if (e != hipSuccess) return e;
+    grid = (per_cu * a.n_cu) & ~7;
+    if (grid < 8) grid = 8;
+    const int need = (a.n_tiles + 7) & ~7;
+    if (grid > need) grid = need;
+  }
+  hipLaunchKernelGGL((stage_kernel<R, NF, WZ, RHS, READ_TN>), dim3(grid), dim3(threads), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename R, int NF>
 hipError_t launch_nf(const StageArgs& a, bool w_zero, bool rhs_only, bool read_tn, hipStream_t s) {
-  dim3 grid(a.n_tiles), block(kCell * a.tile_layers);
-  if (rhs_only) {
-    if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<R, NF, false, true, false>), grid, block, 0, s, a);
-  } else if (read_tn) {
-    if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<R, NF, false, false, true>), grid, block, 0, s, a);
-  } else {
-    if (w_zero) hipLaunchKernelGGL((stage_kernel<R, NF, true, false, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<R, NF, false, false, false>), grid, block, 0, s, a);
-  }
-  return hipGetLastError();
+  if (rhs_only) return w_zero ? launch_mode<R, NF, true, true, false>(a, s) : launch_mode<R, NF, false, true, false>(a, s);
+  if (read_tn) return w_zero ? launch_mode<R, NF, true, false, true>(a, s) : launch_mode<R, NF, false, false, true>(a, s);
+  return w_zero ? launch_mode<R, NF, true, false, false>(a, s) : launch_mode<R, NF, false, false, false>(a, s);
 }
 
 template <typename R>

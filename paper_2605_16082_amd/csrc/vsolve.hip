@@ -24,7 +24,9 @@
 // without pivoting: forward sweep D'_l = D_l - B_l D'_{l-1}^-1 C_{l-1}, with
 // the LU of D'_l shared by all fields; E_l = D'_l^-1 [:, 3:6] and
 // y_l = D'_l^-1 r'_l go to scratch; back substitution
-// x_l = y_l - E_l (C_l x_{l+1}) recomputes C_l from the levels.  All FP64.
+// x_l = y_l - E_l (C_l x_{l+1}) recomputes C_l from the levels.  The
+// arithmetic type C is double (the FP64 and FP32-state/FP64-solve forms) or
+// float (the FP32-everywhere form); the scratch then holds values of type C.
 #include "internal.h"
 
 namespace sdg {
@@ -46,25 +48,28 @@ __device__ __forceinline__ int sidx(int a, int b) {
   return a == b ? a : (a + b == 1 ? 3 : (a + b == 2 ? 4 : 5));
 }
 
+template <typename C>
 struct LayerGeo {
-  double dz[3];
-  double hbar;
+  C dz[3];
+  C hbar;
 };
 
-__device__ __forceinline__ void load_layer(const DevMesh& m, size_t lt, LayerGeo& g) {
+template <typename C>
+__device__ __forceinline__ void load_layer(const DevMesh& m, size_t lt, LayerGeo<C>& g) {
   const size_t LS = (size_t)m.n_lslots;
 #pragma unroll
-  for (int v = 0; v < 3; ++v) g.dz[v] = m.zl[v * LS + lt] - m.zl[v * LS + lt + kCell];
-  g.hbar = (g.dz[0] + g.dz[1] + g.dz[2]) * (1.0 / 3.0);
+  for (int v = 0; v < 3; ++v) g.dz[v] = (C)(m.zl[v * LS + lt] - m.zl[v * LS + lt + kCell]);
+  g.hbar = (g.dz[0] + g.dz[1] + g.dz[2]) * (C)(1.0 / 3.0);
 }
 
-__device__ __forceinline__ void vertical_stiffness(const LayerGeo& g, double Jh, double kv[6]) {
+template <typename C>
+__device__ __forceinline__ void vertical_stiffness(const LayerGeo<C>& g, C Jh, C kv[6]) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) kv[i] = 0.0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    const double l0 = kL0[q], l1 = kL1[q], l2 = kL2[q];
-    const double inv = kTw[q] / (l0 * g.dz[0] + l1 * g.dz[1] + l2 * g.dz[2]);
+    const C l0 = (C)kL0[q], l1 = (C)kL1[q], l2 = (C)kL2[q];
+    const C inv = (C)kTw[q] / (l0 * g.dz[0] + l1 * g.dz[1] + l2 * g.dz[2]);
     kv[0] += l0 * l0 * inv;
     kv[1] += l1 * l1 * inv;
     kv[2] += l2 * l2 * inv;
@@ -76,22 +81,24 @@ __device__ __forceinline__ void vertical_stiffness(const LayerGeo& g, double Jh,
   for (int i = 0; i < 6; ++i) kv[i] *= Jh;
 }
 
-__device__ __forceinline__ void mass_z(const LayerGeo& g, double Jh, double mz[6]) {
-  const double s = Jh * (1.0 / 120.0);
-  const double* dz = g.dz;
-  mz[0] = s * (3.0 * dz[0] + dz[1] + dz[2]);
-  mz[1] = s * (dz[0] + 3.0 * dz[1] + dz[2]);
-  mz[2] = s * (dz[0] + dz[1] + 3.0 * dz[2]);
-  mz[3] = s * (dz[0] + dz[1] + 0.5 * dz[2]);
-  mz[4] = s * (dz[0] + dz[2] + 0.5 * dz[1]);
-  mz[5] = s * (dz[1] + dz[2] + 0.5 * dz[0]);
+template <typename C>
+__device__ __forceinline__ void mass_z(const LayerGeo<C>& g, C Jh, C mz[6]) {
+  const C s = Jh * (C)(1.0 / 120.0);
+  const C* dz = g.dz;
+  mz[0] = s * ((C)3.0 * dz[0] + dz[1] + dz[2]);
+  mz[1] = s * (dz[0] + (C)3.0 * dz[1] + dz[2]);
+  mz[2] = s * (dz[0] + dz[1] + (C)3.0 * dz[2]);
+  mz[3] = s * (dz[0] + dz[1] + (C)0.5 * dz[2]);
+  mz[4] = s * (dz[0] + dz[2] + (C)0.5 * dz[1]);
+  mz[5] = s * (dz[1] + dz[2] + (C)0.5 * dz[0]);
 }
 
-__device__ __forceinline__ double penalty(double eta, double ka, double kb, double ha, double hb) {
-  return eta * 0.5 * (ka + kb) / fmin(ha, hb);
+template <typename C>
+__device__ __forceinline__ C penalty(C eta, C ka, C kb, C ha, C hb) {
+  return eta * (C)0.5 * (ka + kb) / (ha < hb ? ha : hb);
 }
 
-template <typename S, int NF>
+template <typename S, typename C, int NF>
 __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const DevMesh& m = a.m;
   const int cell = xcd_tile(blockIdx.x, m.n_cells);
@@ -103,56 +110,56 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const size_t SL = (size_t)m.n_slots;
   const size_t p0 = (size_t)m.cell_base[cell] + lane;
   const size_t lt0 = (size_t)m.cell_lbase[cell] + lane;
-  const double Jh = m.geo[G_JH * m.n_col_slots + c];
-  const double dt = a.dt, eta = a.eta;
+  const C Jh = (C)m.geo[G_JH * m.n_col_slots + c];
+  const C dt = (C)a.dt, eta = (C)a.eta;
   const double* __restrict__ kap = a.kappa;
   const S* __restrict__ Tst = static_cast<const S*>(a.Tstar);
   S* __restrict__ Tout = static_cast<S*>(a.Tout);
-  double* __restrict__ Esc = a.scratch;
-  double* __restrict__ Ysc = a.scratch + 18 * SL;
-  const double sd = Jh * (1.0 / 12.0), so = Jh * (1.0 / 24.0);   // M_h diagonal / off-diagonal
+  C* __restrict__ Esc = reinterpret_cast<C*>(a.scratch);
+  C* __restrict__ Ysc = Esc + 18 * SL;
+  const C sd = Jh * (C)(1.0 / 12.0), so = Jh * (C)(1.0 / 24.0);   // M_h diagonal / off-diagonal
 
   // ---------------- forward sweep ----------------
-  LayerGeo gc, gn;
+  LayerGeo<C> gc, gn;
   load_layer(m, lt0, gc);
-  double kvp[6], kvc[6];        // Kv of layers l-1 and l
-  double Ep[6][3];              // E_{l-1}
-  double yp[NF][6];             // y_{l-1}
-  double kp = 0.0, hp = 0.0;    // kappa, hbar of layer l-1
+  C kvp[6], kvc[6];        // Kv of layers l-1 and l
+  C Ep[6][3];              // E_{l-1}
+  C yp[NF][6];             // y_{l-1}
+  C kp = (C)0.0, hp = (C)0.0;    // kappa, hbar of layer l-1
   vertical_stiffness(gc, Jh, kvc);
 
   for (int l = 0; l < N; ++l) {
     const size_t p = p0 + (size_t)l * kCell;
-    const double kc = kap[l];
+    const C kc = (C)kap[l];
     const bool below = l < N - 1;
-    double kn = 0.0;
+    C kn = (C)0.0;
     if (below) {
       load_layer(m, lt0 + (size_t)(l + 1) * kCell, gn);
-      kn = kap[l + 1];
+      kn = (C)kap[l + 1];
     }
-    double mz[6];
+    C mz[6];
     mass_z(gc, Jh, mz);
 
     // diagonal block
-    double d[6][6];
+    C d[6][6];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const double mm = mz[sidx(i, j)], kk = dt * kc * kvc[sidx(i, j)];
-        d[i][j] = (2.0 / 3.0) * mm + kk;
-        d[i][j + 3] = (1.0 / 3.0) * mm - kk;
-        d[i + 3][j] = (1.0 / 3.0) * mm - kk;
-        d[i + 3][j + 3] = (2.0 / 3.0) * mm + kk;
+        const C mm = mz[sidx(i, j)], kk = dt * kc * kvc[sidx(i, j)];
+        d[i][j] = (C)(2.0 / 3.0) * mm + kk;
+        d[i][j + 3] = (C)(1.0 / 3.0) * mm - kk;
+        d[i + 3][j] = (C)(1.0 / 3.0) * mm - kk;
+        d[i + 3][j + 3] = (C)(2.0 / 3.0) * mm + kk;
       }
-    const double sig_u = l > 0 ? penalty(eta, kp, kc, hp, gc.hbar) : 0.0;
-    const double sig_d = below ? penalty(eta, kc, kn, gc.hbar, gn.hbar) : 0.0;
+    const C sig_u = l > 0 ? penalty(eta, kp, kc, hp, gc.hbar) : (C)0.0;
+    const C sig_d = below ? penalty(eta, kc, kn, gc.hbar, gn.hbar) : (C)0.0;
     if (l > 0) {
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const double hk = 0.5 * dt * kc * kvc[sidx(i, j)];
+          const C hk = (C)0.5 * dt * kc * kvc[sidx(i, j)];
           d[i][j] += -hk + dt * sig_u * (i == j ? sd : so);
           d[i][j + 3] += hk;
         }
@@ -162,60 +169,60 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const double hk = 0.5 * dt * kc * kvc[sidx(i, j)];
+          const C hk = (C)0.5 * dt * kc * kvc[sidx(i, j)];
           d[i + 3][j] += hk;
           d[i + 3][j + 3] += -hk + dt * sig_d * (i == j ? sd : so);
         }
     }
 
     // right-hand sides r = M T*
-    double r[NF][6];
+    C r[NF][6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      double t[6];
+      C t[6];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) t[i] = (double)Tst[(size_t)(f * 6 + i) * SL + p];
+      for (int i = 0; i < 6; ++i) t[i] = (C)Tst[(size_t)(f * 6 + i) * SL + p];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        double at = 0.0, ab = 0.0;
+        C at = (C)0.0, ab = (C)0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           at += mz[sidx(i, j)] * t[j];
           ab += mz[sidx(i, j)] * t[j + 3];
         }
-        r[f][i] = (2.0 / 3.0) * at + (1.0 / 3.0) * ab;
-        r[f][i + 3] = (1.0 / 3.0) * at + (2.0 / 3.0) * ab;
+        r[f][i] = (C)(2.0 / 3.0) * at + (C)(1.0 / 3.0) * ab;
+        r[f][i + 3] = (C)(1.0 / 3.0) * at + (C)(2.0 / 3.0) * ab;
       }
     }
 
     // Schur complement with the layer above
     if (l > 0) {
       // B_l = dt [-kp Kvp/2 | kp Kvp/2 - sig_u S]  (3 x 6)
-      double Bm[3][6];
+      C Bm[3][6];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const double hk = 0.5 * dt * kp * kvp[sidx(i, j)];
+          const C hk = (C)0.5 * dt * kp * kvp[sidx(i, j)];
           Bm[i][j] = -hk;
           Bm[i][j + 3] = hk - dt * sig_u * (i == j ? sd : so);
         }
       // C_{l-1} = dt [kc Kvc/2 - sig_u S | -kc Kvc/2]  (3 x 6)
-      double Cm[3][6];
+      C Cm[3][6];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          const double hk = 0.5 * dt * kc * kvc[sidx(i, j)];
+          const C hk = (C)0.5 * dt * kc * kvc[sidx(i, j)];
           Cm[i][j] = hk - dt * sig_u * (i == j ? sd : so);
           Cm[i][j + 3] = -hk;
         }
-      double P[3][3];
+      C P[3][3];
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          double acc = 0.0;
+          C acc = (C)0.0;
 #pragma unroll
           for (int k = 0; k < 6; ++k) acc += Bm[i][k] * Ep[k][j];
           P[i][j] = acc;
@@ -224,7 +231,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-          double acc = 0.0;
+          C acc = (C)0.0;
 #pragma unroll
           for (int k = 0; k < 3; ++k) acc += P[i][k] * Cm[k][j];
           d[i][j] -= acc;
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
       for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
-          double acc = 0.0;
+          C acc = (C)0.0;
 #pragma unroll
           for (int k = 0; k < 6; ++k) acc += Bm[i][k] * yp[f][k];
           r[f][i] -= acc;
@@ -243,30 +250,30 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     // LU of d (no pivoting), in place
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      const double inv = 1.0 / d[k][k];
+      const C inv = (C)1.0 / d[k][k];
 #pragma unroll
       for (int i = k + 1; i < 6; ++i) {
-        const double li = d[i][k] * inv;
+        const C li = d[i][k] * inv;
         d[i][k] = li;
 #pragma unroll
         for (int j = k + 1; j < 6; ++j) d[i][j] -= li * d[k][j];
       }
     }
     // solve for E = d^-1 e_{3,4,5} and y = d^-1 r
-    double Ec[6][3];
+    C Ec[6][3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-      double z[6];
+      C z[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        double acc = (i == q + 3) ? 1.0 : 0.0;
+        C acc = (i == q + 3) ? (C)1.0 : (C)0.0;
 #pragma unroll
         for (int k = 0; k < i; ++k) acc -= d[i][k] * z[k];
         z[i] = acc;
       }
 #pragma unroll
       for (int i = 5; i >= 0; --i) {
-        double acc = z[i];
+        C acc = z[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) acc -= d[i][k] * z[k];
         z[i] = acc / d[i][i];
@@ -276,17 +283,17 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      double z[6];
+      C z[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        double acc = r[f][i];
+        C acc = r[f][i];
 #pragma unroll
         for (int k = 0; k < i; ++k) acc -= d[i][k] * z[k];
         z[i] = acc;
       }
 #pragma unroll
       for (int i = 5; i >= 0; --i) {
-        double acc = z[i];
+        C acc = z[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) acc -= d[i][k] * z[k];
         z[i] = acc / d[i][i];
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
 
   // ---------------- back substitution ----------------
   // x_{N-1} = y_{N-1} (still in yp)
-  double xn[NF][6];
+  C xn[NF][6];
   {
     const size_t p = p0 + (size_t)(N - 1) * kCell;
 #pragma unroll
@@ -329,40 +336,40 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
       }
   }
   // kvp, kp, hp describe layer N-1 now
-  LayerGeo gl;
+  LayerGeo<C> gl;
   for (int l = N - 2; l >= 0; --l) {
     const size_t p = p0 + (size_t)l * kCell;
     load_layer(m, lt0 + (size_t)l * kCell, gl);
-    const double kl = kap[l];
-    const double sig_d = penalty(eta, kl, kp, gl.hbar, hp);
+    const C kl = (C)kap[l];
+    const C sig_d = penalty(eta, kl, kp, gl.hbar, hp);
     // C_l = dt [kp Kv_{l+1}/2 - sig_d S | -kp Kv_{l+1}/2]
-    double Cm[3][6];
+    C Cm[3][6];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        const double hk = 0.5 * dt * kp * kvp[sidx(i, j)];
+        const C hk = (C)0.5 * dt * kp * kvp[sidx(i, j)];
         Cm[i][j] = hk - dt * sig_d * (i == j ? sd : so);
         Cm[i][j + 3] = -hk;
       }
-    double E[6][3];
+    C E[6][3];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) E[i][q] = Esc[(size_t)(i * 3 + q) * SL + p];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      double cx[3];
+      C cx[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        double acc = 0.0;
+        C acc = (C)0.0;
 #pragma unroll
         for (int j = 0; j < 6; ++j) acc += Cm[i][j] * xn[f][j];
         cx[i] = acc;
       }
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        const double y = Ysc[(size_t)(f * 6 + i) * SL + p];
+        const C y = Ysc[(size_t)(f * 6 + i) * SL + p];
         xn[f][i] = y - (E[i][0] * cx[0] + E[i][1] * cx[1] + E[i][2] * cx[2]);
       }
     }
@@ -376,14 +383,14 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   }
 }
 
-template <typename S>
+template <typename S, typename C>
 hipError_t launch_s(const SolveArgs& a, hipStream_t s) {
   dim3 grid(a.m.n_cells), block(kCell);
   switch (a.n_fields) {
-    case 1: hipLaunchKernelGGL((vsolve_kernel<S, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((vsolve_kernel<S, 2>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((vsolve_kernel<S, 3>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((vsolve_kernel<S, 4>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((vsolve_kernel<S, C, 1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((vsolve_kernel<S, C, 2>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((vsolve_kernel<S, C, 3>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((vsolve_kernel<S, C, 4>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -391,9 +398,10 @@ hipError_t launch_s(const SolveArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, hipStream_t s) {
+hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, hipStream_t s) {
   if (a.m.n_cells == 0) return hipSuccess;
-  return fp32_state ? launch_s<float>(a, s) : launch_s<double>(a, s);
+  if (!fp32_state) return launch_s<double, double>(a, s);
+  return fp32_solve ? launch_s<float, float>(a, s) : launch_s<float, double>(a, s);
 }
 
 }  // namespace sdg

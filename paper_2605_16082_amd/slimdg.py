@@ -68,7 +68,7 @@ class Layout(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile_layers", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+    _fields_ = [("tile_layers", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -307,19 +307,20 @@ class SlimDG:
         _check(self.lib.sdg_sync(self.ctx))
 
     # -- launch shape, autotuning, graph replay -------------------------------
-    def get_tuning(self) -> tuple[int, int]:
+    def get_tuning(self) -> tuple[int, int, int]:
+        """(tile_layers, xcd_remap, persistent) of the stage kernel."""
         t = Tuning()
         _check(self.lib.sdg_get_tuning(self.ctx, ctypes.byref(t)))
-        return int(t.tile_layers), int(t.xcd_remap)
+        return int(t.tile_layers), int(t.xcd_remap), int(t.persistent)
 
-    def set_tuning(self, tile_layers: int, xcd_remap: int = 1):
-        t = Tuning(int(tile_layers), int(xcd_remap))
+    def set_tuning(self, tile_layers: int, xcd_remap: int = 1, persistent: int = 0):
+        t = Tuning(int(tile_layers), int(xcd_remap), int(persistent))
         _check(self.lib.sdg_set_tuning(self.ctx, ctypes.byref(t)))
 
-    def autotune(self, reps: int = 5) -> tuple[int, int]:
+    def autotune(self, reps: int = 5) -> tuple[int, int, int]:
         t = Tuning()
         _check(self.lib.sdg_autotune(self.ctx, int(reps), ctypes.byref(t)))
-        return int(t.tile_layers), int(t.xcd_remap)
+        return int(t.tile_layers), int(t.xcd_remap), int(t.persistent)
 
     def graph_capture_step(self):
         _check(self.lib.sdg_graph_capture_step(self.ctx))

@@ -32,7 +32,8 @@ def ensemble():
     return _W["e"]
 
 
-SHAPES = [(4, 1), (1, 0), (2, 1), (1, 1), (4, 0), (2, 0)]
+SHAPES = [(4, 1, 0), (1, 0, 1), (2, 1, 1), (1, 1, 0), (4, 0, 1), (2, 0, 0),
+          (1, 0, 0), (4, 1, 1), (2, 1, 0), (1, 1, 1), (4, 0, 0), (2, 0, 1)]
 
 
 @pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32])
@@ -42,9 +43,9 @@ def test_launch_shape_does_not_change_results(precision):
     rng = np.random.default_rng(3)
     Ts = s.scatter(w.T0 + 0.1 * rng.standard_normal(w.T0.shape))
     ref = None
-    for tl, x in SHAPES:
-        s.set_tuning(tl, x)
-        assert s.get_tuning() == (tl, x)
+    for tl, x, pers in SHAPES:
+        s.set_tuning(tl, x, pers)
+        assert s.get_tuning() == (tl, x, pers)
         outs = [s.rk_stage(k, state, Ts) for k in range(3)] + [s.rhs_3d(Ts)]
         s.sync()
         got = [s.gather(o) for o in outs]
@@ -52,15 +53,38 @@ def test_launch_shape_does_not_change_results(precision):
             ref = got
         else:
             for a, b in zip(got, ref):
-                assert np.array_equal(a, b), (tl, x)
+                assert np.array_equal(a, b), (tl, x, pers)
+
+
+def test_persistent_grid_walks_many_tiles():
+    """A mesh with several times more tiles than the chip holds at once, so
+    every persistent workgroup walks several tiles: bitwise the same stage
+    output as one workgroup per tile, for every tile height and remap."""
+    w = W.config1(n=100, n_layers=20, seed=4)
+    s, U, kappa, state = P.from_workload(w)
+    rng = np.random.default_rng(8)
+    Ts = s.scatter(w.T0 + 0.1 * rng.standard_normal(w.T0.shape))
+    for tl in (1, 2, 4):
+        outs = []
+        for x, pers in ((1, 0), (1, 1), (0, 1)):
+            s.set_tuning(tl, x, pers)
+            outs.append(s.rk_stage(2, state, Ts))
+        s.sync()
+        for o in outs[1:]:
+            assert torch_equal(o, outs[0]), tl
+
+
+def torch_equal(a, b):
+    return bool((a == b).all().item())
 
 
 def test_bad_tuning_rejected():
     w, m = ensemble()
     s = P.from_workload(w)[0]
-    with pytest.raises(P.SlimDGError) as e:
-        s.set_tuning(3, 1)
-    assert e.value.status == -1
+    for bad in [(3, 1, 0), (2, 2, 0), (2, 1, 2)]:
+        with pytest.raises(P.SlimDGError) as e:
+            s.set_tuning(*bad)
+        assert e.value.status == -1, bad
 
 
 def test_autotune_keeps_results():
@@ -68,7 +92,7 @@ def test_autotune_keeps_results():
     a = P.from_workload(w)
     b = P.from_workload(w)
     choice = a[0].autotune(reps=3)
-    assert choice[0] in (1, 2, 4) and choice[1] in (0, 1)
+    assert choice[0] in (1, 2, 4) and choice[1] in (0, 1) and choice[2] in (0, 1)
     a[0].step(2)
     b[0].step(2)
     a[0].sync()

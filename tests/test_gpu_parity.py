@@ -192,6 +192,45 @@ def test_fp32_state_form(name):
     assert np.all(err <= 2e-5), err
 
 
+_REF10 = {}
+
+
+@pytest.mark.parametrize("precision", [P.SDG_FP32_STATE_FP64_SOLVE, P.SDG_FP32])
+def test_fp32_forms_config1_run(precision):
+    """Config 1 in full (10 steps) in the FP32-state/FP64-solve form and in
+    FP32 everywhere, against the FP64 oracle: per-field max-norm error within
+    2e-5 of the field's maximum, total mass within 1e-6 relative."""
+    w, m = case("config1")
+    if "ref" not in _REF10:
+        ref = w.T0
+        for _ in range(w.n_steps):
+            ref = O.step(m, w.U, w.kappa, ref, w.dt, w.t_ext, w.penalty)
+        _REF10["ref"] = ref
+        _REF10["mass"] = O.mass(m, ref)
+    s, U, kappa, state = upload(w, precision)
+    s.step(w.n_steps)
+    s.sync()
+    err = rel_err(s.gather(state), _REF10["ref"])
+    dm = np.abs(s.mass(state)[0] - _REF10["mass"]) / np.abs(_REF10["mass"])
+    print("precision", precision, "10-step error", err, "mass", dm)
+    assert np.all(err <= 2e-5), err
+    assert np.all(dm <= 1e-6), dm
+
+
+@pytest.mark.parametrize("name", ["config1", "deep_ragged"])
+def test_fp32_everywhere_solve(name):
+    """The FP32 column solve against the FP64 oracle's dense solve."""
+    w, m = case(name)
+    s, U, kappa, state = upload(w, P.SDG_FP32)
+    rng = np.random.default_rng([4, 1])
+    Ts_np = w.T0 + 0.1 * rng.standard_normal(w.T0.shape)
+    out = s.vertical_implicit_solve(s.scatter(Ts_np))
+    s.sync()
+    err = rel_err(s.gather(out), O.implicit_solve(m, w.kappa, w.dt, Ts_np, w.penalty))
+    print(name, "fp32 solve", err)
+    assert np.all(err <= 1e-5), err
+
+
 @pytest.fixture(scope="module")
 def big():
     w = W.config2()

@@ -18,6 +18,7 @@ from .prism_mesh import (  # noqa: F401
     config1,
     config2,
     config4,
+    config5,
     small_ensemble,
     tiny,
     ragged,

@@ -257,6 +257,16 @@ def config1(seed: int = 0, n: int = 30, n_layers: int = 10) -> Workload:
                     t_ext=np.zeros(1), n_steps=10)
 
 
+def config5(seed: int = 0, n: int = 158, n_layers: int = 20) -> Workload:
+    """Differentiation form: the config1 tracer problem on 158 x 158 split
+    squares (49,928 triangles) x 20 sigma layers (998,560 prisms), FP64, 200
+    steps with a checkpoint every 20."""
+    w = config1(seed=seed, n=n, n_layers=n_layers)
+    w.name = "config5"
+    w.n_steps = 200
+    return w
+
+
 def config2(seed: int = 0, n: int = 316, n_layers: int = 30) -> Workload:
     """FP64 vs FP32 at scale: n=316 split squares (199,712 triangles), 30 sigma
     layers (5,991,360 prisms), 4 advected scalars: u, v (the rotation's
