@@ -190,12 +190,15 @@ sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
 /* Launch shape of the fused stage kernel (the paper's section 4.1 shows
  * throughput depending on the column block shape; here the library measures
- * it).  Results do not depend on it.
- * tile_layers: layers per workgroup of 64 columns (1, 2 or 4; default 2);
+ * it).  Results do not depend on it (bitwise).
+ * tile_layers: 1, 2 or 4 = layers per workgroup of 64 columns, one thread per
+ *   prism (default 2); 8, 16 or 32 = one wavefront walks that many layers of
+ *   a cell, prefetching the next layer into LDS while computing the current;
  * xcd_remap: 1 = give each XCD one contiguous range of tiles (default);
  * persistent: 1 = launch only as many workgroups as the device holds at once,
  *   each walking tiles with a stride (default 0: one workgroup per tile).
- * The adjoint stages use tile_layers and xcd_remap and ignore persistent. */
+ * The adjoint stages use tile_layers (2 in place of a walk) and xcd_remap,
+ * and ignore persistent. */
 typedef struct {
   int32_t tile_layers;
   int32_t xcd_remap;
@@ -205,7 +208,7 @@ typedef struct {
 sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out);
 sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* tuning);
 
-/* Time every stage-kernel launch shape (3 tile heights x XCD remap off/on x
+/* Time every stage-kernel launch shape (6 tile heights x XCD remap off/on x
  * persistent off/on), each over reps repetitions of the three stages of a
  * step on the set fields and velocity (the fields are only read; the stages
  * write the workspace stage buffers), and keep the fastest.  Synchronises

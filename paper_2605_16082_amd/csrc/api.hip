@@ -45,7 +45,7 @@ struct Plan {
   int64_t n_prisms = 0, n_slots = 0, n_lslots = 0;
   std::vector<int32_t> cell_base, cell_lbase, cell_depth, member_off;
   std::vector<int64_t> zoff;  // per column: first row of its levels in desc.zlev
-  int n_tiles[kTileChoices] = {0, 0, 0};
+  int n_tiles[kTileChoices] = {};
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_stage_a, o_stage_b, o_scratch,
@@ -218,7 +218,7 @@ struct sdg_ctx {
   Plan plan;
   DevMesh dm{};
   char* ws = nullptr;
-  WgTile* tiles[kTileChoices] = {nullptr, nullptr, nullptr};
+  WgTile* tiles[kTileChoices] = {};
   // launch shape of the stage kernel (chosen by sdg_set_tuning / sdg_autotune)
   int tile_choice = 1;   // index into kTileLayerOptions (2 layers)
   int xcd = 1;
@@ -395,7 +395,11 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
       {P.o_tiles[0], tiles[0].data(), sizeof(WgTile) * tiles[0].size()},
       {P.o_tiles[1], tiles[1].data(), sizeof(WgTile) * tiles[1].size()},
       {P.o_tiles[2], tiles[2].data(), sizeof(WgTile) * tiles[2].size()},
+      {P.o_tiles[3], tiles[3].data(), sizeof(WgTile) * tiles[3].size()},
+      {P.o_tiles[4], tiles[4].data(), sizeof(WgTile) * tiles[4].size()},
+      {P.o_tiles[5], tiles[5].data(), sizeof(WgTile) * tiles[5].size()},
   };
+  static_assert(kTileChoices == 6, "one copy per tile table");
   for (const Cp& cp : cps) {
     if (cp.bytes == 0) continue;
     hipError_t e = hipMemcpyAsync(ws + cp.off, cp.src, cp.bytes, hipMemcpyHostToDevice, s);
@@ -652,7 +656,7 @@ sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* t) {
   int choice = -1;
   for (int i = 0; i < kTileChoices; ++i)
     if (kTileLayerOptions[i] == t->tile_layers) choice = i;
-  if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2 or 4 (got %d)", t->tile_layers);
+  if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2, 4, 8, 16 or 32 (got %d)", t->tile_layers);
   if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(SDG_E_ARG, "xcd_remap must be 0 or 1");
   if (t->persistent != 0 && t->persistent != 1) return fail(SDG_E_ARG, "persistent must be 0 or 1");
   ctx->tile_choice = choice;
@@ -818,9 +822,11 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   double* zb2 = static_cast<double*>(ctx->stage_a);
   double* zb1 = static_cast<double*>(ctx->stage_b);
   const double* U = static_cast<const double*>(ctx->U);
-  const int tl = kTileLayerOptions[ctx->tile_choice];
-  const WgTile* tiles = ctx->tiles[ctx->tile_choice];
-  const int nt = P.n_tiles[ctx->tile_choice];
+  // the adjoint stages run one thread per prism: a walk segment maps to 2-layer tiles
+  const int choice = ctx->tile_choice < kThreadTileChoices ? ctx->tile_choice : 1;
+  const int tl = kTileLayerOptions[choice];
+  const WgTile* tiles = ctx->tiles[choice];
+  const int nt = P.n_tiles[choice];
   hipStream_t s = ctx->stream;
   hipError_t e = launch_tsolve(ctx->dm, P.F, static_cast<const double*>(dev_z_next), mu, ctx->kappa,
                                ctx->scratch, ctx->dt, ctx->eta, s);

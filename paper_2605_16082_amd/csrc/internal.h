@@ -48,19 +48,23 @@ struct DevMesh {
 };
 
 // A workgroup of the per-prism kernels covers tile_layers consecutive layers
-// of one cell: (cell, first layer).
+// of one cell: (cell, first layer).  Tile heights from kWalkMinLayers up are
+// walked by one wavefront (the column-walk form of the stage kernel); the
+// smaller ones run one thread per prism.
 struct WgTile {
   int32_t cell;
   int32_t layer0;
 };
-constexpr int kTileChoices = 3;                 // tile_layers in {1, 2, 4}
-constexpr int kTileLayerOptions[kTileChoices] = {1, 2, 4};
+constexpr int kTileChoices = 6;
+constexpr int kTileLayerOptions[kTileChoices] = {1, 2, 4, 8, 16, 32};
+constexpr int kWalkMinLayers = 8;
+constexpr int kThreadTileChoices = 3;           // choices 0..2 run one thread per prism
 
 struct StageArgs {
   DevMesh m;
   const WgTile* tiles;   // one entry per workgroup: (cell, first layer)
   int32_t n_tiles;
-  int32_t tile_layers;   // layers per workgroup (1, 2 or 4): blockDim = 64 * tile_layers
+  int32_t tile_layers;   // layers per tile: 1, 2, 4 (blockDim 64 * tile_layers) or a walk segment
   int32_t xcd;           // 1: XCD-contiguous tile order
   int32_t persistent;    // 1: grid of resident workgroups walking the tiles
   int32_t n_cu;          // compute units of the device (persistent grid size)

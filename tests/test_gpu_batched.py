@@ -32,8 +32,11 @@ def ensemble():
     return _W["e"]
 
 
-SHAPES = [(4, 1, 0), (1, 0, 1), (2, 1, 1), (1, 1, 0), (4, 0, 1), (2, 0, 0),
-          (1, 0, 0), (4, 1, 1), (2, 1, 0), (1, 1, 1), (4, 0, 0), (2, 0, 1)]
+# every (tile height, XCD remap, persistent) shape; heights from 8 up are the
+# column-walk kernel
+SHAPES = [(4, 1, 0), (1, 0, 1), (8, 1, 0), (2, 1, 1), (16, 0, 1), (1, 1, 0), (32, 1, 1), (4, 0, 1),
+          (2, 0, 0), (8, 0, 1), (1, 0, 0), (16, 1, 0), (4, 1, 1), (32, 0, 0), (2, 1, 0), (8, 1, 1),
+          (1, 1, 1), (16, 0, 0), (4, 0, 0), (32, 1, 0), (2, 0, 1), (8, 0, 0), (16, 1, 1), (32, 0, 1)]
 
 
 @pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32])
@@ -64,7 +67,7 @@ def test_persistent_grid_walks_many_tiles():
     s, U, kappa, state = P.from_workload(w)
     rng = np.random.default_rng(8)
     Ts = s.scatter(w.T0 + 0.1 * rng.standard_normal(w.T0.shape))
-    for tl in (1, 2, 4):
+    for tl in (1, 2, 4, 8, 16, 32):
         outs = []
         for x, pers in ((1, 0), (1, 1), (0, 1)):
             s.set_tuning(tl, x, pers)
@@ -81,7 +84,7 @@ def torch_equal(a, b):
 def test_bad_tuning_rejected():
     w, m = ensemble()
     s = P.from_workload(w)[0]
-    for bad in [(3, 1, 0), (2, 2, 0), (2, 1, 2)]:
+    for bad in [(3, 1, 0), (64, 1, 0), (2, 2, 0), (2, 1, 2)]:
         with pytest.raises(P.SlimDGError) as e:
             s.set_tuning(*bad)
         assert e.value.status == -1, bad
@@ -92,7 +95,7 @@ def test_autotune_keeps_results():
     a = P.from_workload(w)
     b = P.from_workload(w)
     choice = a[0].autotune(reps=3)
-    assert choice[0] in (1, 2, 4) and choice[1] in (0, 1) and choice[2] in (0, 1)
+    assert choice[0] in (1, 2, 4, 8, 16, 32) and choice[1] in (0, 1) and choice[2] in (0, 1)
     a[0].step(2)
     b[0].step(2)
     a[0].sync()

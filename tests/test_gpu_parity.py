@@ -238,12 +238,15 @@ def big():
     return w, m
 
 
-@pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32_STATE_FP64_SOLVE])
-def test_config2_sampled_parity(big, precision):
-    """Full-size config (199,712 columns x 30 layers, 4 fields) in the launch
-    configuration the benchmark times, checked on sampled prisms/columns."""
+@pytest.mark.parametrize("precision,shape", [(P.SDG_FP64, None), (P.SDG_FP32_STATE_FP64_SOLVE, None),
+                                             (P.SDG_FP64, (16, 1, 0)), (P.SDG_FP32_STATE_FP64_SOLVE, (8, 1, 1))])
+def test_config2_sampled_parity(big, precision, shape):
+    """Full-size config (199,712 columns x 30 layers, 4 fields), checked on
+    sampled prisms/columns: in the launch shape the autotuner picks for the
+    benchmark, and in column-walk shapes."""
     w, m = big
     s, U, kappa, state = upload(w, precision)
+    print("tuning", s.autotune(reps=2) if shape is None else s.set_tuning(*shape))
     tol = TOL64 if precision == P.SDG_FP64 else 5e-5
     rng = np.random.default_rng([2, 9])
     Ts_np = w.T0 + 0.05 * rng.standard_normal(w.T0.shape)
