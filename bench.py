@@ -377,7 +377,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "stage_kernel (fused rhs + SSP-RK3 stage), mean of the 3 stage launches",
+            "kernel": ("walk_kernel (column walk" if r64["tuning"]["tile_layers"] >= 8 else "stage_kernel (one thread per prism")
+                      + ", fused rhs + SSP-RK3 stage), mean of the 3 stage launches",
             "achieved": r64["stage_GBps"],
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",

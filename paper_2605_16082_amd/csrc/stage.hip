@@ -639,9 +639,13 @@ __device__ __forceinline__ void fetch_rows(const char* base, uint32_t rowb, int 
   }
 }
 
+struct WalkCell {
+  int cell, N, depth;
+  uint32_t base, lbase;
+};
 // One layer L of this cell into an LDS slot.
 template <typename R, int NF, bool WZ, bool READ_TN>
-__device__ __forceinline__ void walk_fetch(const StageArgs& a, int cell, int L, R* slot, int lane) {
+__device__ __forceinline__ void walk_fetch(const StageArgs& a, const WalkCell& wc, int L, R* slot, int lane) {
   using Ly = WalkLayout<R, NF, WZ, READ_TN>;
   constexpr int kLanesPerRow = kCell / Ly::kPerLoad;
   const DevMesh& m = a.m;
@@ -649,8 +653,8 @@ __device__ __forceinline__ void walk_fetch(const StageArgs& a, int cell, int L, 
   const uint32_t chunk = (uint32_t)(lane % kLanesPerRow) * 16u;
   const uint32_t rowb = (uint32_t)((size_t)m.n_slots * sizeof(R));
   const uint32_t lrowb = (uint32_t)((size_t)m.n_lslots * sizeof(R));
-  const uint32_t pb = ((uint32_t)m.cell_base[cell] + (uint32_t)L * kCell) * (uint32_t)sizeof(R) + chunk;
-  const uint32_t zb = ((uint32_t)m.cell_lbase[cell] + (uint32_t)(L + 1) * kCell) * (uint32_t)sizeof(R) + chunk;
+  const uint32_t pb = (wc.base + (uint32_t)L * kCell) * (uint32_t)sizeof(R) + chunk;
+  const uint32_t zb = (wc.lbase + (uint32_t)(L + 1) * kCell) * (uint32_t)sizeof(R) + chunk;
   fetch_rows<R, Ly::kPerLoad>(static_cast<const char*>(a.Ts), rowb, 6 * NF, pb, sub, slot + Ly::kTs * kCell);
   fetch_rows<R, Ly::kPerLoad>(static_cast<const char*>(a.U), rowb, Ly::kNU, pb, sub, slot + Ly::kU * kCell);
   fetch_rows<R, Ly::kPerLoad>(reinterpret_cast<const char*>(zl_of<R>(m)), lrowb, 3, zb, sub, slot + Ly::kZ * kCell);
@@ -658,9 +662,19 @@ __device__ __forceinline__ void walk_fetch(const StageArgs& a, int cell, int L, 
     fetch_rows<R, Ly::kPerLoad>(static_cast<const char*>(a.Tn), rowb, 6 * NF, pb, sub, slot + Ly::kTn * kCell);
 }
 
-// vmcnt(0) / lgkmcnt(0) alone (gfx9 s_waitcnt encoding).
-__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-__device__ __forceinline__ void wait_lgkm() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// vmcnt(0) / lgkmcnt(0) alone (gfx9 s_waitcnt encoding), each also a
+// compiler memory barrier so no LDS read is moved above the wait that makes
+// its data valid, nor a copy into LDS above the reads it must follow.
+__device__ __forceinline__ void wait_vm() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  asm volatile("" ::: "memory");
+}
+__device__ __forceinline__ void wait_lgkm() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+}
+// Keeps later LDS reads below a just-issued copy (compiler barrier only).
+__device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
 
 // State a wavefront carries from one layer of its walk to the next.
 template <typename R, int NF>
@@ -677,12 +691,13 @@ struct WalkCarry {
 // neighbour traces one field ahead.
 template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
 __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& cg, const LatMeta<R> (&lm)[3],
-                                           int cell, int lane, int N, int depth, int l, const R* cur, R* nxt,
+                                           const WalkCell& wc, int lane, int l, const R* cur, R* nxt,
                                            WalkCarry<R, NF>& cs) {
+  const int N = wc.N, depth = wc.depth;
   using Ly = WalkLayout<R, NF, WZ, READ_TN>;
   const DevMesh& m = a.m;
   const size_t S = (size_t)m.n_slots;
-  const uint32_t p = (uint32_t)m.cell_base[cell] + (uint32_t)l * kCell + lane;
+  const uint32_t p = wc.base + (uint32_t)l * kCell + lane;
   const uint32_t po = p * (uint32_t)sizeof(R);
   const bool below = l + 1 < depth;   // wavefront-uniform
   const bool active = l < N;
@@ -693,7 +708,8 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
 #pragma unroll
   for (int e = 0; e < 3; ++e) lat_nb<R>(a, lm[e], e, l, po, nb[e]);
   wait_lgkm();
-  if (below) walk_fetch<R, NF, WZ, READ_TN>(a, cell, l + 1, nxt, lane);
+  if (below) walk_fetch<R, NF, WZ, READ_TN>(a, wc, l + 1, nxt, lane);
+  mem_order();
   phase();
 
   R zb[3], dz[3];
@@ -796,13 +812,18 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
     const WgTile tile = a.tiles[r.t];
     const int cell = tile.cell;
     const int c = cell * kCell + lane;
-    const int N = m.nlay[c];
-    const int depth = (m.cell_base[cell + 1] - m.cell_base[cell]) / kCell;
+    WalkCell wc;
+    wc.cell = cell;
+    wc.N = m.nlay[c];
+    wc.base = (uint32_t)m.cell_base[cell];
+    wc.lbase = (uint32_t)m.cell_lbase[cell];
+    wc.depth = (int)(((uint32_t)m.cell_base[cell + 1] - wc.base) / kCell);
+    const int depth = wc.depth;
     const int l0 = tile.layer0;
     const int l1 = min(l0 + a.tile_layers, depth);
     const size_t S = (size_t)m.n_slots;
     const size_t LS = (size_t)m.n_lslots;
-    const uint32_t pc = (uint32_t)m.cell_base[cell] + lane;
+    const uint32_t pc = wc.base + lane;
     const R* __restrict__ Ts = static_cast<const R*>(a.Ts);
     const R* __restrict__ U = static_cast<const R*>(a.U);
     const R* __restrict__ zl = zl_of<R>(m);
@@ -814,10 +835,10 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
 
     // layer l0 into slot0; the top face of l0 from the layer above (global)
     wait_lgkm();
-    walk_fetch<R, NF, WZ, READ_TN>(a, cell, l0, slot0, lane);
+    walk_fetch<R, NF, WZ, READ_TN>(a, wc, l0, slot0, lane);
     WalkCarry<R, NF> cs;
     {
-      const uint32_t lt = (uint32_t)m.cell_lbase[cell] + (uint32_t)l0 * kCell + lane;
+      const uint32_t lt = wc.lbase + (uint32_t)l0 * kCell + lane;
 #pragma unroll
       for (int v3 = 0; v3 < 3; ++v3) cs.zt[v3] = ldb(zl + v3 * LS, lt * (uint32_t)sizeof(R));
       const uint32_t pup = (l0 > 0 ? pc + (uint32_t)(l0 - 1) * kCell : pc) * (uint32_t)sizeof(R);
@@ -850,8 +871,8 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
     }
     // layers in pairs so that each half names its slots statically
     for (int l = l0; l < l1; l += 2) {
-      walk_layer<R, NF, WZ, RHS, READ_TN>(a, cg, lm, cell, lane, N, depth, l, slot0, slot1, cs);
-      if (l + 1 < l1) walk_layer<R, NF, WZ, RHS, READ_TN>(a, cg, lm, cell, lane, N, depth, l + 1, slot1, slot0, cs);
+      walk_layer<R, NF, WZ, RHS, READ_TN>(a, cg, lm, wc, lane, l, slot0, slot1, cs);
+      if (l + 1 < l1) walk_layer<R, NF, WZ, RHS, READ_TN>(a, cg, lm, wc, lane, l + 1, slot1, slot0, cs);
     }
     // the last layer may have started a copy into a slot the next tile reuses
     wait_vm();
