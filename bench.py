@@ -167,6 +167,7 @@ def precision_forms(w, steps, torch, P_mod):
     oracle to 1e-12 stage by stage and solve by solve), the difference of
     each field's total mass over (max |T_f| * volume), and the time per step."""
     s, U, kappa, x = P_mod.from_workload(w, P_mod.SDG_FP64)
+    s.autotune(reps=2)
     s.step(1)
     s.set_fields(x.copy_(s.scatter(w.T0)))
     t = event_time(torch, lambda: s.step(steps))
@@ -178,6 +179,7 @@ def precision_forms(w, steps, torch, P_mod):
     for key, prec in (("fp32_state_fp64_solve", P_mod.SDG_FP32_STATE_FP64_SOLVE),
                       ("fp32_everywhere", P_mod.SDG_FP32)):
         s, U, kappa, x = P_mod.from_workload(w, prec)
+        s.autotune(reps=2)
         s.step(1)
         s.set_fields(x.copy_(s.scatter(w.T0)))
         t = event_time(torch, lambda: s.step(steps))
@@ -237,6 +239,7 @@ def adjoint_form(torch, P_mod, W, n_steps=200, every=20):
     checkpoint every `every` steps, against the plain forward run."""
     w = W.config5()
     s, U, kappa, x = P_mod.from_workload(w)
+    s.autotune(reps=2)
     s.step(2)
     s.set_fields(x.copy_(s.scatter(w.T0)))
     t_fwd = event_time(torch, lambda: s.step(n_steps))
