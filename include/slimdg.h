@@ -136,8 +136,10 @@ int sdg_abi_version(void);
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* sdg_last_error(void);
 
-/* Validate a mesh description and report sizes.  Host only; no GPU needed.
- * SDG_E_ARG / SDG_E_MESH with a message on failure. */
+/* Validate a mesh description and report sizes: columns grouped in cells of
+ * 64, each as deep as its deepest column (the paper's section 2.1.1 cell
+ * structure).  Host only; no GPU needed.  SDG_E_ARG / SDG_E_MESH with a
+ * message on failure. */
 sdg_status sdg_query_layout(const sdg_mesh_desc* mesh, sdg_layout* out);
 
 /* Slot of each prism in natural order: host_slots[off[c] + l] for column c,
@@ -152,40 +154,56 @@ sdg_status sdg_destroy(sdg_ctx* ctx);
 
 /* Validate, lay out and copy the mesh into the caller's device workspace
  * (>= workspace_bytes, 256-byte aligned), then compute the per-column
- * geometry on the device.  Synchronises the stream.  Any previously set
- * velocity / diffusivity / fields are forgotten. */
+ * geometry on the device (the extruded triangle mesh of section 1; J_h of
+ * the 2D mass matrix of section 2.3).  Synchronises the stream.  Any
+ * previously set velocity / diffusivity / fields are forgotten. */
 sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_workspace,
                            size_t workspace_bytes);
 
+/* Time step, interior-penalty factor of the vertical diffusion (section 2.4
+ * system) and exterior values of the open boundaries.  Host struct, copied. */
 sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* params);
 
-/* Nodal velocity [3][6][n_slots] (u, v, w) in the state precision. */
+/* Nodal velocity [3][6][n_slots] (u, v, w) in the state precision: the
+ * transport velocity of the section 1.1 tracer equation. */
 sdg_status sdg_set_velocity(sdg_ctx* ctx, const void* dev_uvw);
 
-/* Vertical diffusivity per layer index, [max_layers] doubles [m^2/s]. */
+/* Vertical diffusivity per layer index, [max_layers] doubles [m^2/s] (the
+ * kappa of the section 1.1 tracer equation, constant in each layer). */
 sdg_status sdg_set_diffusivity(sdg_ctx* ctx, const double* dev_kappa);
 
-/* State advanced in place by sdg_step, [n_fields][6][n_slots]. */
+/* State advanced in place by sdg_step, [n_fields][6][n_slots]: nodal tracer
+ * values, top three nodes then bottom three (the Algorithm 1 node split). */
 sdg_status sdg_set_fields(sdg_ctx* ctx, void* dev_state);
 
-/* dev_L = M^-1 R(dev_T).  Needs velocity and params.  dev_L must not alias dev_T. */
+/* dev_L = M^-1 R(dev_T): the horizontal flux operator of section 2.2 in its
+ * explicit form (volume term plus upwind lateral and horizontal interface
+ * fluxes, block-diagonal mass matrix).  Needs velocity and params.  dev_L
+ * must not alias dev_T. */
 sdg_status sdg_rhs_3d(sdg_ctx* ctx, const void* dev_T, void* dev_L);
 
-/* dev_Tout = a dev_Tn + b (dev_Ts + dt L(dev_Ts)) for stage 0, 1, 2.
- * Stage 0 does not read dev_Tn.  dev_Tout must not alias dev_Ts or dev_Tn. */
+/* dev_Tout = a dev_Tn + b (dev_Ts + dt L(dev_Ts)) for stage 0, 1, 2 of
+ * SSP-RK3 in Shu-Osher form, (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3): the
+ * explicit stage update of section 2.2.  Stage 0 does not read dev_Tn.
+ * dev_Tout must not alias dev_Ts or dev_Tn. */
 sdg_status sdg_rk_stage(sdg_ctx* ctx, int stage, const void* dev_Tn, const void* dev_Ts,
                         void* dev_Tout);
 
-/* (M - dt A) dev_Tout = M dev_Tstar per column.  Needs diffusivity and
- * params.  dev_Tout may alias dev_Tstar. */
+/* (M - dt A) dev_Tout = M dev_Tstar per column: the implicit vertical
+ * diffusion system of sections 1.2 and 2.2, block tridiagonal with the
+ * sparsity of section 2.4, solved in FP64 (FP32 in SDG_FP32) by block
+ * Thomas.  Needs diffusivity and params.  dev_Tout may alias dev_Tstar. */
 sdg_status sdg_vertical_implicit_solve(sdg_ctx* ctx, const void* dev_Tstar, void* dev_Tout);
 
 /* n_steps x (3 rk_stage + vertical_implicit_solve) on the set fields, in
- * place, using two stage buffers inside the workspace. */
+ * place, using two stage buffers inside the workspace: the horizontally
+ * explicit, vertically implicit splitting of section 1.2 taken as Lie
+ * splitting (three explicit stages, then one implicit vertical step). */
 sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
 
-/* host_mass[m * n_fields + f] = sum over member m's prisms of 1^T M T_f.
- * Synchronises the stream. */
+/* host_mass[m * n_fields + f] = sum over member m's prisms of 1^T M T_f, in
+ * FP64 with a fixed summation order (the conserved quantity of the section
+ * 1.1 tracer equation).  Synchronises the stream. */
 sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
 /* Launch shape of the fused stage kernel (the paper's section 4.1 shows
@@ -216,7 +234,8 @@ sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* tuning);
 sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen);
 
 /* Capture one sdg_step (three stages and the column solve, on the set fields)
- * into a HIP graph; replaces any previous capture.  Waits for the context
+ * into a HIP graph (section 3.3 of the paper discusses launch latency of
+ * short kernels); replaces any previous capture.  Waits for the context
  * stream first.  Any later set_* / set_tuning / mesh_upload call invalidates
  * the capture (sdg_graph_launch then returns SDG_E_STATE). */
 sdg_status sdg_graph_capture_step(sdg_ctx* ctx);
@@ -224,16 +243,20 @@ sdg_status sdg_graph_capture_step(sdg_ctx* ctx);
 /* Replay the captured step n_steps times on the context stream. */
 sdg_status sdg_graph_launch(sdg_ctx* ctx, int n_steps);
 
-/* Y = M X (inverse = 0) or Y = M^-1 X (inverse != 0), prism by prism, for a
- * [n_fields][6][n_slots] array in the state precision.  Y may alias X. */
+/* Y = M X (inverse = 0) or Y = M^-1 X (inverse != 0), prism by prism (the
+ * block-diagonal DG mass matrix of section 2.2), for a [n_fields][6][n_slots]
+ * array in the state precision.  Y may alias X. */
 sdg_status sdg_apply_mass(sdg_ctx* ctx, const void* dev_X, void* dev_Y, int inverse);
 
 /* host_out[m * n_fields + f] = sum over member m's prisms of X_f^T M Y_f
- * (FP64, fixed summation order).  Synchronises the stream. */
+ * (FP64, fixed summation order; the M inner product the adjoint uses).
+ * Synchronises the stream. */
 sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double* host_out);
 
-/* Reverse of one sdg_step (FP64 contexts only), in the variable Z = M^-1 lambda
- * where lambda = dJ/dx is the adjoint state:
+/* Reverse of one sdg_step (FP64 contexts only): not in the paper; it is the
+ * exact transpose of the section 2.2 stage equations and of the section 2.4
+ * column system, in the variable Z = M^-1 lambda where lambda = dJ/dx is the
+ * adjoint state:
  *   mu     = (M - dt A^T)^-1 M Z^{n+1}                     (transposed column solve)
  *   dkappa[l] += dt mu^T (dA/dkappa_l) x^{n+1}              (if dev_dkappa != NULL)
  *   Z^n    = reverse SSP-RK3 stages with M^-1 R_lin^T       (R_lin: the advective
