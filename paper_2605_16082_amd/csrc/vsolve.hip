@@ -23,7 +23,7 @@
 // which is the half-block sparsity drawn in section 2.4.  Block Thomas
 // without pivoting: forward sweep D'_l = D_l - B_l D'_{l-1}^-1 C_{l-1}, with
 // the LU of D'_l shared by all fields; E_l = D'_l^-1 [:, 3:6] and
-// y_l = D'_l^-1 r'_l go to scratch; back substitution
+// y_l = D'_l^-1 r'_l go to scratch (as 16-byte pairs); back substitution
 // x_l = y_l - E_l (C_l x_{l+1}) recomputes C_l from the levels.  The
 // arithmetic type C is double (the FP64 and FP32-state/FP64-solve forms) or
 // float (the FP32-everywhere form); the scratch then holds values of type C.
@@ -93,6 +93,15 @@ __device__ __forceinline__ void mass_z(const LayerGeo<C>& g, C Jh, C mz[6]) {
   mz[5] = s * (dz[1] + dz[2] + (C)0.5 * dz[0]);
 }
 
+// Scratch entries go in pairs: value pair k of slot p at pair index k * n_slots
+// + p, so each lane moves 16 bytes (FP64) per instruction and the
+// wavefront's accesses stay contiguous.  Values: E_l row-major (18), then
+// y_l field by field (6 each).
+template <typename C>
+struct alignas(2 * sizeof(C)) CPair {
+  C lo, hi;
+};
+
 template <typename C>
 __device__ __forceinline__ C penalty(C eta, C ka, C kb, C ha, C hb) {
   return eta * (C)0.5 * (ka + kb) / (ha < hb ? ha : hb);
@@ -115,13 +124,26 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const double* __restrict__ kap = a.kappa;
   const S* __restrict__ Tst = static_cast<const S*>(a.Tstar);
   S* __restrict__ Tout = static_cast<S*>(a.Tout);
-  C* __restrict__ Esc = reinterpret_cast<C*>(a.scratch);
-  C* __restrict__ Ysc = Esc + 18 * SL;
+  CPair<C>* __restrict__ Psc = reinterpret_cast<CPair<C>*>(a.scratch);
+  constexpr int kNV = 18 + 6 * NF;   // values per slot (even)
   const C sd = Jh * (C)(1.0 / 12.0), so = Jh * (C)(1.0 / 24.0);   // M_h diagonal / off-diagonal
 
   // ---------------- forward sweep ----------------
-  LayerGeo<C> gc, gn;
+  // A layer's stage values and the next layer's level heights are loaded
+  // one layer ahead (at clamped, always valid slots), before this layer's
+  // scratch stores, so their latency is covered by this layer's arithmetic.
+  auto load_t = [&](int l, C (&t)[NF][6]) {
+    const size_t p = p0 + (size_t)l * kCell;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) t[f][i] = (C)Tst[(size_t)(f * 6 + i) * SL + p];
+  };
+  LayerGeo<C> gc, gn, gpre;
   load_layer(m, lt0, gc);
+  load_layer(m, lt0 + (size_t)(N > 1 ? 1 : 0) * kCell, gpre);
+  C tpre[NF][6];
+  load_t(0, tpre);
   C kvp[6], kvc[6];        // Kv of layers l-1 and l
   C Ep[6][3];              // E_{l-1}
   C yp[NF][6];             // y_{l-1}
@@ -132,11 +154,15 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     const size_t p = p0 + (size_t)l * kCell;
     const C kc = (C)kap[l];
     const bool below = l < N - 1;
-    C kn = (C)0.0;
-    if (below) {
-      load_layer(m, lt0 + (size_t)(l + 1) * kCell, gn);
-      kn = (C)kap[l + 1];
-    }
+    C t[NF][6];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) t[f][i] = tpre[f][i];
+    gn = gpre;
+    load_t(l + 1 < N ? l + 1 : N - 1, tpre);
+    load_layer(m, lt0 + (size_t)(l + 2 < N ? l + 2 : N - 1) * kCell, gpre);
+    const C kn = below ? (C)kap[l + 1] : (C)0.0;
     C mz[6];
     mass_z(gc, Jh, mz);
 
@@ -179,16 +205,13 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     C r[NF][6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      C t[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) t[i] = (C)Tst[(size_t)(f * 6 + i) * SL + p];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         C at = (C)0.0, ab = (C)0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
-          at += mz[sidx(i, j)] * t[j];
-          ab += mz[sidx(i, j)] * t[j + 3];
+          at += mz[sidx(i, j)] * t[f][j];
+          ab += mz[sidx(i, j)] * t[f][j + 3];
         }
         r[f][i] = (C)(2.0 / 3.0) * at + (C)(1.0 / 3.0) * ab;
         r[f][i + 3] = (C)(1.0 / 3.0) * at + (C)(2.0 / 3.0) * ab;
@@ -247,10 +270,13 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
         }
     }
 
-    // LU of d (no pivoting), in place
+    // LU of d (no pivoting), in place; the pivots' reciprocals are kept so
+    // the triangular solves below multiply instead of divide
+    C dinv[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       const C inv = (C)1.0 / d[k][k];
+      dinv[k] = inv;
 #pragma unroll
       for (int i = k + 1; i < 6; ++i) {
         const C li = d[i][k] * inv;
@@ -276,7 +302,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
         C acc = z[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) acc -= d[i][k] * z[k];
-        z[i] = acc / d[i][i];
+        z[i] = acc * dinv[i];
       }
 #pragma unroll
       for (int i = 0; i < 6; ++i) Ec[i][q] = z[i];
@@ -296,21 +322,27 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
         C acc = z[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) acc -= d[i][k] * z[k];
-        z[i] = acc / d[i][i];
+        z[i] = acc * dinv[i];
       }
 #pragma unroll
-      for (int i = 0; i < 6; ++i) {
-        yp[f][i] = z[i];
-        Ysc[(size_t)(f * 6 + i) * SL + p] = z[i];
-      }
+      for (int i = 0; i < 6; ++i) yp[f][i] = z[i];
     }
+    {
+      C sv[kNV];
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+      for (int i = 0; i < 6; ++i)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        Ep[i][q] = Ec[i][q];
-        Esc[(size_t)(i * 3 + q) * SL + p] = Ec[i][q];
-      }
+        for (int q = 0; q < 3; ++q) {
+          Ep[i][q] = Ec[i][q];
+          sv[i * 3 + q] = Ec[i][q];
+        }
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) sv[18 + f * 6 + i] = yp[f][i];
+#pragma unroll
+      for (int k = 0; k < kNV / 2; ++k) Psc[(size_t)k * SL + p] = CPair<C>{sv[2 * k], sv[2 * k + 1]};
+    }
     // advance the carried layer quantities
 #pragma unroll
     for (int i = 0; i < 6; ++i) kvp[i] = kvc[i];
@@ -335,11 +367,28 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
         Tout[(size_t)(f * 6 + i) * SL + p] = (S)yp[f][i];
       }
   }
-  // kvp, kp, hp describe layer N-1 now
-  LayerGeo<C> gl;
+  // kvp, kp, hp describe layer N-1 now.  E_l, y_l and the layer's levels
+  // are loaded one layer ahead.
+  auto load_sv = [&](int l, C (&sv)[kNV], LayerGeo<C>& g) {
+    const size_t p = p0 + (size_t)l * kCell;
+#pragma unroll
+    for (int k = 0; k < kNV / 2; ++k) {
+      const CPair<C> v = Psc[(size_t)k * SL + p];
+      sv[2 * k] = v.lo;
+      sv[2 * k + 1] = v.hi;
+    }
+    load_layer(m, lt0 + (size_t)l * kCell, g);
+  };
+  C svpre[kNV];
+  LayerGeo<C> glpre;
+  load_sv(N > 1 ? N - 2 : 0, svpre, glpre);
   for (int l = N - 2; l >= 0; --l) {
     const size_t p = p0 + (size_t)l * kCell;
-    load_layer(m, lt0 + (size_t)l * kCell, gl);
+    C sv[kNV];
+#pragma unroll
+    for (int k = 0; k < kNV; ++k) sv[k] = svpre[k];
+    const LayerGeo<C> gl = glpre;
+    load_sv(l > 0 ? l - 1 : 0, svpre, glpre);
     const C kl = (C)kap[l];
     const C sig_d = penalty(eta, kl, kp, gl.hbar, hp);
     // C_l = dt [kp Kv_{l+1}/2 - sig_d S | -kp Kv_{l+1}/2]
@@ -356,7 +405,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
-      for (int q = 0; q < 3; ++q) E[i][q] = Esc[(size_t)(i * 3 + q) * SL + p];
+      for (int q = 0; q < 3; ++q) E[i][q] = sv[i * 3 + q];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       C cx[3];
@@ -369,8 +418,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
       }
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        const C y = Ysc[(size_t)(f * 6 + i) * SL + p];
-        xn[f][i] = y - (E[i][0] * cx[0] + E[i][1] * cx[1] + E[i][2] * cx[2]);
+        xn[f][i] = sv[18 + f * 6 + i] - (E[i][0] * cx[0] + E[i][1] * cx[1] + E[i][2] * cx[2]);
       }
     }
 #pragma unroll
