@@ -26,3 +26,4 @@ from .prism_dg import (  # noqa: F401
     mass,
     boundary_flux,
 )
+from . import column_dv  # noqa: F401,E402
