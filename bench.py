@@ -161,6 +161,29 @@ def field_errors(torch, x, ref):
     return (d / ref.abs().amax(dim=(1, 2))).tolist()
 
 
+def column_dv_form(w, torch, P_mod, reps=20):
+    """The matrix-free column solves (section 2.3) on the benchmark mesh: D_vu
+    with 2 components (the horizontal pressure gradient) and D_vd with 1 (w),
+    in FP64 and with float state.  Algorithmic bytes per launch: the right-hand
+    side read and the solution written once (12 values per prism and
+    component) plus nlayers and J_h per column."""
+    out = {}
+    for prec, tag in ((P_mod.SDG_FP64, "fp64"), (P_mod.SDG_FP32_STATE_FP64_SOLVE, "fp32_state")):
+        s = P_mod.SlimDG(P_mod.Mesh.from_workload(w, prec, n_fields=1))
+        es = 8 if prec == P_mod.SDG_FP64 else 4
+        for kind, name, nc in ((P_mod.SDG_DV_VU, "D_vu", 2), (P_mod.SDG_DV_VD, "D_vd", 1)):
+            F = torch.randn((nc, 6, s.n_slots), dtype=s.dtype, device=s.device)
+            X = torch.empty_like(F)
+            t = time_calls(torch, lambda: s.column_dv_solve(kind, F, X), reps)
+            by = 12 * nc * w.n_prisms * es + w.n_cols * (4 + 8)
+            out[f"{name}_{tag}"] = {"n_comp": nc, "t_s": t, "bytes_per_launch": int(by),
+                                    "GBps": by / t / 1e9, "frac": by / t / HBM_PEAK}
+            del F, X
+        del s
+        torch.cuda.empty_cache()
+    return out
+
+
 def precision_forms(w, steps, torch, P_mod):
     """The precision forms after `steps` steps from the same initial state:
     per-field max-norm error against the FP64 path (which matches the FP64
@@ -347,8 +370,10 @@ def main():
     if not args.no_fp32:
         r32 = run_gpu(w, P_mod.SDG_FP32_STATE_FP64_SOLVE, args.steps, args.warmup, torch, P_mod)
         log("fp32 state / fp64 solve", json.dumps(r32))
-    forms = batched = adjoint = None
+    forms = batched = adjoint = dv = None
     if not args.no_extra:
+        dv = column_dv_form(w, torch, P_mod)
+        log("column dv", json.dumps(dv))
         forms = precision_forms(w, 100, torch, P_mod)
         log("precision forms", json.dumps(forms))
         adjoint = adjoint_form(torch, P_mod, W)
@@ -408,6 +433,8 @@ def main():
             "stage_frac": r32["stage_GBps"] * 1e9 / HBM_PEAK, "solve_GBps": r32["solve_GBps"],
             "tuning": r32["tuning"],
         }
+    if dv is not None:
+        out["column_dv"] = dv
     if forms is not None:
         out["precision_forms_after_100_steps"] = forms
     if not args.no_extra:

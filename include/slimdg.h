@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 2
+#define SDG_ABI_VERSION 3
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -90,6 +90,13 @@ typedef enum {
   SDG_FP32 = 1,
   SDG_FP32_STATE_FP64_SOLVE = 2
 } sdg_precision;
+
+/* The two column systems of the matrix-free solvers (sdg_column_dv_solve). */
+typedef enum {
+  SDG_DV_VU = 0,   /* D_vu: horizontal pressure gradient system, solved from the surface down */
+  SDG_DV_VD = 1    /* D_vd: vertical velocity system, solved from the seabed up */
+} sdg_dv_kind;
+#define SDG_DV_MAX_COMP 4
 
 typedef struct sdg_ctx sdg_ctx; /* opaque */
 
@@ -267,6 +274,26 @@ sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double*
  * workspace stage buffers. */
 sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_next,
                             double* dev_dkappa);
+
+/* Matrix-free column solve of section 2.3 ("Matrix-free solvers"): in every
+ * column, D x = F with D the block matrix the paper prints for a 3-layer
+ * column, continued to the column's depth -- 1/2 times 3x3 blocks that are
+ * multiples of M_h = J_h/24 [2 1 1; 1 2 1; 1 1 2]:
+ *   SDG_DV_VU (D_vu, Algorithm 1): per layer l, top rows  2M x_bot(l-1) - M x_top(l) - M x_bot(l),
+ *                                               bottom rows M x_top(l) - M x_bot(l);
+ *             the discrete dx/dz = f with x = 0 at the surface, solved top-down;
+ *   SDG_DV_VD (D_vd): per layer l, top rows    M x_top(l) - M x_bot(l),
+ *                                  bottom rows M x_top(l) + M x_bot(l) - 2M x_top(l+1);
+ *             the discrete dx/dz = f with x = 0 at the seabed, solved bottom-up.
+ * dev_F, dev_x: [n_comp][6][n_slots] in the state precision (cell layout; per
+ * prism the three top-face nodes, then the three bottom-face nodes), device
+ * pointers owned by the caller; dev_x may equal dev_F (in place).  n_comp in
+ * 1..SDG_DV_MAX_COMP (e.g. 2 for the horizontal pressure gradient, 1 for w).
+ * Arithmetic in double except in SDG_FP32 contexts.  Padding slots are
+ * neither read nor written.  Needs an uploaded mesh (SDG_E_STATE otherwise);
+ * an unknown kind, n_comp out of range or a NULL pointer gives SDG_E_ARG.
+ * Enqueued on the context stream; does not synchronise. */
+sdg_status sdg_column_dv_solve(sdg_ctx* ctx, int kind, int n_comp, const void* dev_F, void* dev_x);
 
 /* Wait for the context's stream and report any asynchronous HIP error. */
 sdg_status sdg_sync(sdg_ctx* ctx);

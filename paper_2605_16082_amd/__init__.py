@@ -5,6 +5,9 @@ The compute path is libslimdg.so (``csrc/``, C ABI in ``include/slimdg.h``);
 """
 
 from .slimdg import (  # noqa: F401
+    SDG_DV_MAX_COMP,
+    SDG_DV_VD,
+    SDG_DV_VU,
     SDG_FP32,
     SDG_FP32_STATE_FP64_SOLVE,
     SDG_FP64,

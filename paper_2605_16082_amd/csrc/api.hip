@@ -850,6 +850,22 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   return SDG_OK;
 }
 
+sdg_status sdg_column_dv_solve(sdg_ctx* ctx, int kind, int n_comp, const void* dev_F, void* dev_x) {
+  if (!ctx || !dev_F || !dev_x) return fail(SDG_E_ARG, "sdg_column_dv_solve: NULL argument");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_column_dv_solve needs an uploaded mesh");
+  if (kind != SDG_DV_VU && kind != SDG_DV_VD)
+    return fail(SDG_E_ARG, "sdg_column_dv_solve: unknown kind %d", kind);
+  if (n_comp < 1 || n_comp > SDG_DV_MAX_COMP)
+    return fail(SDG_E_ARG, "sdg_column_dv_solve: n_comp must be in 1..%d (got %d)", SDG_DV_MAX_COMP, n_comp);
+  DeviceGuard g(ctx->device);
+  const Plan& P = ctx->plan;
+  hipError_t e = launch_column_dv(ctx->dm, kind == SDG_DV_VU, n_comp, dev_F, dev_x, P.fp32,
+                                  P.prec == SDG_FP32, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "column D_v solve launch");
+  g_err.clear();
+  return SDG_OK;
+}
+
 sdg_status sdg_sync(sdg_ctx* ctx) {
   if (!ctx) return fail(SDG_E_ARG, "context is NULL");
   DeviceGuard g(ctx->device);

@@ -95,6 +95,9 @@ hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,
                         bool read_tn, hipStream_t s);
 hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, hipStream_t s);
+// Matrix-free D_vu (down = true) / D_vd column solves; fp32_arith only with fp32_state.
+hipError_t launch_column_dv(const DevMesh& m, bool down, int n_comp, const void* F, void* X, bool fp32_state,
+                            bool fp32_arith, hipStream_t s);
 hipError_t launch_column_mass(const DevMesh& m, const void* T, int n_fields, bool fp32,
                               double* col_mass, hipStream_t s);
 hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fields,

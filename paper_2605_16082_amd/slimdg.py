@@ -18,6 +18,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libslimdg.so")
 
 SDG_FP64, SDG_FP32, SDG_FP32_STATE_FP64_SOLVE = 0, 1, 2
+SDG_DV_VU, SDG_DV_VD = 0, 1
+SDG_DV_MAX_COMP = 4
 STATUS_NAMES = {0: "SDG_OK", -1: "SDG_E_ARG", -2: "SDG_E_MESH", -3: "SDG_E_HIP", -4: "SDG_E_STATE",
                 -5: "SDG_E_UNSUPPORTED", -6: "SDG_E_NUMERIC", -7: "SDG_E_WORKSPACE"}
 
@@ -27,6 +29,7 @@ EXPORTED = (
     "sdg_set_fields", "sdg_rhs_3d", "sdg_rk_stage", "sdg_vertical_implicit_solve", "sdg_step",
     "sdg_mass", "sdg_sync", "sdg_get_tuning", "sdg_set_tuning", "sdg_autotune",
     "sdg_graph_capture_step", "sdg_graph_launch", "sdg_apply_mass", "sdg_m_dot", "sdg_step_adjoint",
+    "sdg_column_dv_solve",
 )
 
 
@@ -120,6 +123,7 @@ def load_library(path: str | None = None):
         "sdg_apply_mass": ([vp, vp, vp, i32], i32),
         "sdg_m_dot": ([vp, vp, vp, vp], i32),
         "sdg_step_adjoint": ([vp, vp, vp, vp, vp], i32),
+        "sdg_column_dv_solve": ([vp, i32, i32, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -354,6 +358,16 @@ class SlimDG:
         _check(self.lib.sdg_step_adjoint(self.ctx, _ptr(z_next), _ptr(z_out),
                                          None if x_next is None else _ptr(x_next),
                                          None if dkappa is None else _ptr(dkappa)))
+
+    # -- matrix-free column solves -------------------------------------------------
+    def column_dv_solve(self, kind: int, F, out=None):
+        """x with D x = F per column (kind SDG_DV_VU or SDG_DV_VD); F (n_comp, 6, n_slots)."""
+        n_comp = int(F.shape[0])
+        out = self.zeros(n_comp) if out is None else out
+        self._check_nodal(F, n_comp)
+        self._check_nodal(out, n_comp)
+        _check(self.lib.sdg_column_dv_solve(self.ctx, int(kind), n_comp, _ptr(F), _ptr(out)))
+        return out
 
 
 def from_workload(w, precision: int = SDG_FP64, device: int = 0):
