@@ -338,6 +338,8 @@ def main():
     ap.add_argument("--layers", type=int, default=30)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the precision-form, batched and adjoint measurements")
+    ap.add_argument("--column-dv-only", action="store_true",
+                    help="time only the matrix-free column solves and print their JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device twice (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -364,6 +366,9 @@ def main():
     w = W.config2(n=args.n, n_layers=args.layers)
     log(f"workload built in {time.perf_counter() - t0:.1f} s: {w.n_cols} columns, {w.n_prisms} prisms, "
         f"{w.n_fields} fields")
+    if args.column_dv_only:
+        print(json.dumps({"column_dv": column_dv_form(w, torch, P_mod)}), flush=True)
+        return
     r64 = run_gpu(w, P_mod.SDG_FP64, args.steps, args.warmup, torch, P_mod)
     log("fp64", json.dumps(r64))
     r32 = None
