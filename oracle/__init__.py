@@ -27,3 +27,4 @@ from .prism_dg import (  # noqa: F401
     boundary_flux,
 )
 from . import column_dv  # noqa: F401,E402
+from . import split_imex  # noqa: F401,E402
