@@ -233,6 +233,7 @@ template <typename R>
 struct LatNb {
   uint32_t no[4];
   R uo[4], vo[4];
+  bool lds;          // column walk: no[] are offsets into the layer's LDS slot
 };
 
 template <typename R>
@@ -251,6 +252,7 @@ __device__ __forceinline__ void lat_nb(const StageArgs& a, const LatMeta<R>& M, 
   nb.no[1] = nB * rs + pno;
   nb.no[2] = nb.no[0] + 3u * rs;
   nb.no[3] = nb.no[1] + 3u * rs;
+  nb.lds = false;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     nb.uo[j] = ldb(U, nb.no[j]);
@@ -266,6 +268,7 @@ struct LatF {
   R up[3][2], um[3][2];
   uint32_t no[4];
   bool interior;
+  bool lds;
 };
 
 template <typename R>
@@ -279,6 +282,7 @@ __device__ __forceinline__ void lat_factors(const LatMeta<R>& M, const LatNb<R>&
   const R Le = wall ? R(0) : M.Le;
 #pragma unroll
   for (int j = 0; j < 4; ++j) F.no[j] = nb.no[j];
+  F.lds = nb.lds;
   R un[4] = {nx * u[A] + ny * v[A], nx * u[B] + ny * v[B], nx * u[A + 3] + ny * v[A + 3],
              nx * u[B + 3] + ny * v[B + 3]};
 #pragma unroll
@@ -676,6 +680,76 @@ __device__ __forceinline__ void wait_lgkm() {
 // Keeps later LDS reads below a just-issued copy (compiler barrier only).
 __device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
 
+template <typename R>
+__device__ __forceinline__ R lds_at(const R* slot, uint32_t byte_off) {
+  return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(slot) + byte_off);
+}
+
+// Column-walk form of lat_nb.  The layer's stage input and velocity of all
+// 64 columns of the cell are already in the LDS slot `cur`, so a neighbour
+// column of the same cell (most lateral faces of a locality-ordered mesh) is
+// read from there; only a neighbour in another cell is read from global
+// memory.  A face without a live neighbour points at the column's own nodes
+// in LDS (in bounds, unused).
+template <typename R, int kURow>
+__device__ __forceinline__ void lat_nb_walk(const StageArgs& a, const LatMeta<R>& M, int e, int l, uint32_t po,
+                                            int lane, uint32_t cell_base, const R* cur, LatNb<R>& nb) {
+  const size_t S = (size_t)a.m.n_slots;
+  const uint32_t rs = (uint32_t)(S * sizeof(R));
+  const R* __restrict__ U = static_cast<const R*>(a.U);
+  const int A = e, B = (e + 1) % 3;
+  const bool live = M.nslot >= 0 && l < (M.meta >> 2);
+  const int kp = M.meta & 3;
+  const uint32_t nlane = (uint32_t)M.nslot - cell_base;   // < 64 iff the neighbour is in this cell
+  nb.lds = !live || nlane < (uint32_t)kCell;
+  const uint32_t nA = live ? (uint32_t)((kp + 1) % 3) : (uint32_t)A;
+  const uint32_t nB = live ? (uint32_t)kp : (uint32_t)B;
+  if (nb.lds) {
+    constexpr uint32_t row = kCell * sizeof(R);
+    const uint32_t ln = (live ? nlane : (uint32_t)lane) * (uint32_t)sizeof(R);
+    nb.no[0] = nA * row + ln;
+    nb.no[1] = nB * row + ln;
+    nb.no[2] = nb.no[0] + 3u * row;
+    nb.no[3] = nb.no[1] + 3u * row;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      nb.uo[j] = lds_at(cur, (uint32_t)kURow * row + nb.no[j]);
+      nb.vo[j] = lds_at(cur, (uint32_t)(kURow + 6) * row + nb.no[j]);
+    }
+  } else {
+    const uint32_t pno = ((uint32_t)M.nslot + (uint32_t)l * kCell) * (uint32_t)sizeof(R);
+    (void)po;
+    nb.no[0] = nA * rs + pno;
+    nb.no[1] = nB * rs + pno;
+    nb.no[2] = nb.no[0] + 3u * rs;
+    nb.no[3] = nb.no[1] + 3u * rs;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      nb.uo[j] = ldb(U, nb.no[j]);
+      nb.vo[j] = ldb(U + 6 * S, nb.no[j]);
+    }
+  }
+}
+
+// Column-walk form of lat_neighbour: field f's neighbour traces from the LDS
+// slot or from global memory, as lat_nb_walk decided.
+template <typename R, int kTsRow>
+__device__ __forceinline__ void lat_neighbour_walk(const StageArgs& a, const LatF<R>& F, int f, const R* cur,
+                                                   R to[4]) {
+  const R* fb = static_cast<const R*>(a.Ts) + (size_t)(f * 6) * (size_t)a.m.n_slots;
+  const R te = R(a.t_ext[f]);
+  constexpr uint32_t row = kCell * sizeof(R);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    R x;
+    if (F.lds)
+      x = lds_at(cur, (uint32_t)(kTsRow + f * 6) * row + F.no[j]);
+    else
+      x = ldb(fb, F.no[j]);
+    to[j] = F.interior ? x : te;
+  }
+}
+
 // State a wavefront carries from one layer of its walk to the next.
 template <typename R, int NF>
 struct WalkCarry {
@@ -704,9 +778,17 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
   auto own = [&](int row) { return cur[row * kCell + lane]; };
   auto next = [&](int row, R fallback) { return below ? nxt[row * kCell + lane] : fallback; };
 
+  // In-cell neighbours from LDS in FP64 (1.8% faster over a step's three
+  // stages); in FP32 the global form measured 0.9% faster.
+  constexpr bool kNbLds = sizeof(R) == 8;
   LatNb<R> nb[3];
 #pragma unroll
-  for (int e = 0; e < 3; ++e) lat_nb<R>(a, lm[e], e, l, po, nb[e]);
+  for (int e = 0; e < 3; ++e) {
+    if (kNbLds)
+      lat_nb_walk<R, Ly::kU>(a, lm[e], e, l, po, lane, wc.base, cur, nb[e]);
+    else
+      lat_nb<R>(a, lm[e], e, l, po, nb[e]);
+  }
   wait_lgkm();
   if (below) walk_fetch<R, NF, WZ, READ_TN>(a, wc, l + 1, nxt, lane);
   mem_order();
@@ -737,7 +819,7 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
 #pragma unroll
     for (int e = 0; e < 3; ++e) lat_factors<R>(lm[e], nb[e], e, l, dz, u, v, lf[e]);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) lat_neighbour<R>(a, lf[e], 0, to[e]);
+    for (int e = 0; e < 3; ++e) lat_neighbour_walk<R, Ly::kTs>(a, lf[e], 0, cur, to[e]);
     phase();
     wait_vm();   // layer l+1 has arrived
     R ul[3], vl[3], wl[3];
@@ -762,7 +844,7 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
     // field computes
     if (f + 1 < NF) {
 #pragma unroll
-      for (int e = 0; e < 3; ++e) lat_neighbour<R>(a, lf[e], f + 1, ton[e]);
+      for (int e = 0; e < 3; ++e) lat_neighbour_walk<R, Ly::kTs>(a, lf[e], f + 1, cur, ton[e]);
 #pragma unroll
       for (int i = 0; i < 6; ++i)
         tnn[i] = (READ_TN && !Ly::kTnLds) ? ldb(Tn + (size_t)((f + 1) * 6 + i) * S, po) : R(0);
