@@ -70,7 +70,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 3
+#define SDG_ABI_VERSION 4
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -97,6 +97,14 @@ typedef enum {
   SDG_DV_VD = 1    /* D_vd: vertical velocity system, solved from the seabed up */
 } sdg_dv_kind;
 #define SDG_DV_MAX_COMP 4
+
+/* Time step of sdg_step (and of a captured step). */
+typedef enum {
+  SDG_SCHEME_SSPRK3_LIE = 0,  /* three SSP-RK3 stages of the explicit operator, then
+                                 one backward-Euler vertical solve over dt */
+  SDG_SCHEME_SPLIT_IMEX = 1   /* the two-step split-IMEX step of sections 2 and 3:
+                                 vertically implicit over dt/2, then explicit over dt */
+} sdg_time_scheme;
 
 typedef struct sdg_ctx sdg_ctx; /* opaque */
 
@@ -136,6 +144,7 @@ typedef struct {
   const double* t_ext;     /* HOST [n_fields] exterior values on open boundaries; NULL = 0 */
   int32_t w_is_zero;       /* 1: the vertical velocity component is not read */
   int32_t check_finite;    /* 1: sdg_step checks the state after its last step */
+  int32_t time_scheme;     /* sdg_time_scheme of sdg_step (0 = SDG_SCHEME_SSPRK3_LIE) */
 } sdg_params;
 
 int sdg_abi_version(void);
@@ -202,10 +211,20 @@ sdg_status sdg_rk_stage(sdg_ctx* ctx, int stage, const void* dev_Tn, const void*
  * Thomas.  Needs diffusivity and params.  dev_Tout may alias dev_Tstar. */
 sdg_status sdg_vertical_implicit_solve(sdg_ctx* ctx, const void* dev_Tstar, void* dev_Tout);
 
-/* n_steps x (3 rk_stage + vertical_implicit_solve) on the set fields, in
- * place, using two stage buffers inside the workspace: the horizontally
- * explicit, vertically implicit splitting of section 1.2 taken as Lie
- * splitting (three explicit stages, then one implicit vertical step). */
+/* n_steps time steps of the set fields, in place, using two stage buffers
+ * inside the workspace.  The scheme is sdg_params.time_scheme:
+ *   SDG_SCHEME_SSPRK3_LIE: 3 rk_stage + vertical_implicit_solve, the
+ *     horizontally explicit, vertically implicit splitting of section 1.2
+ *     taken as Lie splitting (three explicit stages, then one implicit
+ *     vertical step over dt);
+ *   SDG_SCHEME_SPLIT_IMEX: the two-step split-IMEX step (sections 2 and 3,
+ *     step equation of section 3.2 with M_0 = M_1 = M):
+ *       M x_h = M x_0 + dt/2 (R(x_0) + A x_h)   (vertically implicit, dt/2)
+ *       M x_1 = M x_0 + dt (R(x_h) + A x_h)     (explicit, dt)
+ *     with R the advective residual and A the vertical diffusion operator.
+ *     The second step takes dt M^-1 A x_h = 2 (x_h - y), y the explicit
+ *     half step x_0 + dt/2 M^-1 R(x_0), from the first step's own system.
+ * Deterministic: the same inputs and launch shape give bitwise equal states. */
 sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
 
 /* host_mass[m * n_fields + f] = sum over member m's prisms of 1^T M T_f, in
@@ -260,7 +279,8 @@ sdg_status sdg_apply_mass(sdg_ctx* ctx, const void* dev_X, void* dev_Y, int inve
  * Synchronises the stream. */
 sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double* host_out);
 
-/* Reverse of one sdg_step (FP64 contexts only): not in the paper; it is the
+/* Reverse of one sdg_step (FP64 contexts with SDG_SCHEME_SSPRK3_LIE only,
+ * SDG_E_UNSUPPORTED otherwise): not in the paper; it is the
  * exact transpose of the section 2.2 stage equations and of the section 2.4
  * column system, in the variable Z = M^-1 lambda where lambda = dJ/dx is the
  * adjoint state:

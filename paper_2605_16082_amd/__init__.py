@@ -11,6 +11,8 @@ from .slimdg import (  # noqa: F401
     SDG_FP32,
     SDG_FP32_STATE_FP64_SOLVE,
     SDG_FP64,
+    SDG_SCHEME_SPLIT_IMEX,
+    SDG_SCHEME_SSPRK3_LIE,
     EXPORTED,
     LIB_PATH,
     Mesh,

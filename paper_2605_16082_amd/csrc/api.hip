@@ -242,6 +242,7 @@ struct sdg_ctx {
   double dt = 0.0, eta = 4.0;
   double t_ext[kMaxFields] = {0, 0, 0, 0};
   bool w_zero = false, check_finite = false;
+  int scheme = SDG_SCHEME_SSPRK3_LIE;
   const void* U = nullptr;
   const double* kappa = nullptr;
   void* state = nullptr;
@@ -457,6 +458,9 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
     if (!std::isfinite(v)) return fail(SDG_E_ARG, "t_ext[%d] is not finite", f);
     ctx->t_ext[f] = v;
   }
+  if (p->time_scheme != SDG_SCHEME_SSPRK3_LIE && p->time_scheme != SDG_SCHEME_SPLIT_IMEX)
+    return fail(SDG_E_ARG, "unknown time_scheme %d", p->time_scheme);
+  ctx->scheme = p->time_scheme;
   ctx->dt = p->dt;
   ctx->eta = eta;
   ctx->w_zero = p->w_is_zero != 0;
@@ -504,7 +508,7 @@ sdg_status check_explicit(sdg_ctx* ctx, const char* who) {
   return SDG_OK;
 }
 
-StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, double a, double b) {
+StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, double a, double b, double dt) {
   StageArgs s{};
   s.m = ctx->dm;
   s.tiles = ctx->tiles[ctx->tile_choice];
@@ -519,7 +523,7 @@ StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, d
   s.Tout = Tout;
   s.U = ctx->U;
   for (int f = 0; f < kMaxFields; ++f) s.t_ext[f] = ctx->t_ext[f];
-  s.dt = ctx->dt;
+  s.dt = dt;
   s.a = a;
   s.b = b;
   return s;
@@ -529,13 +533,13 @@ constexpr double kRk[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
 
 sdg_status enqueue_stage(sdg_ctx* ctx, int stage, const void* Tn, const void* Ts, void* Tout,
                          hipStream_t strm) {
-  StageArgs s = stage_args(ctx, Tn, Ts, Tout, kRk[stage][0], kRk[stage][1]);
+  StageArgs s = stage_args(ctx, Tn, Ts, Tout, kRk[stage][0], kRk[stage][1], ctx->dt);
   hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, false, stage > 0, strm);
   if (e != hipSuccess) return hip_fail(e, "rk_stage launch");
   return SDG_OK;
 }
 
-sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, hipStream_t strm) {
+sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt, hipStream_t strm) {
   SolveArgs a{};
   a.m = ctx->dm;
   a.n_fields = ctx->plan.F;
@@ -543,16 +547,41 @@ sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, hipStream_
   a.Tout = Tout;
   a.kappa = ctx->kappa;
   a.scratch = ctx->scratch;
-  a.dt = ctx->dt;
+  a.dt = dt;
   a.eta = ctx->eta;
   hipError_t e = launch_vsolve(a, ctx->plan.fp32, ctx->plan.prec == SDG_FP32, strm);
   if (e != hipSuccess) return hip_fail(e, "vertical solve launch");
   return SDG_OK;
 }
 
-// One step on the set fields: three stages through the two workspace stage
-// buffers, then the column solve back into the state.
+// One split-IMEX step (x_0 = X):
+//   A <- y   = x_0 + dt/2 M^-1 R(x_0)          explicit half step (stage, a = 0, b = 1)
+//   B <- x_h = (M - dt/2 A)^-1 M y             vertically implicit half step
+//   A <- x_0 + x_h - 2 y                       (dt M^-1 A x_h = 2 (x_h - y))
+//   X <- A + x_h + dt M^-1 R(x_h)              explicit full step (stage, a = b = 1)
+sdg_status enqueue_imex_step(sdg_ctx* ctx, hipStream_t strm) {
+  void* X = ctx->state;
+  void* A = ctx->stage_a;
+  void* B = ctx->stage_b;
+  const double h = 0.5 * ctx->dt;
+  StageArgs s1 = stage_args(ctx, nullptr, X, A, 0.0, 1.0, h);
+  hipError_t e = launch_stage(s1, ctx->plan.fp32, ctx->w_zero, false, false, strm);
+  if (e != hipSuccess) return hip_fail(e, "split-IMEX half step launch");
+  sdg_status st = enqueue_solve(ctx, A, B, h, strm);
+  if (st != SDG_OK) return st;
+  e = launch_imex_combine(ctx->dm, X, B, A, ctx->plan.F, ctx->plan.fp32, strm);
+  if (e != hipSuccess) return hip_fail(e, "split-IMEX combine launch");
+  StageArgs s2 = stage_args(ctx, A, B, X, 1.0, 1.0, ctx->dt);
+  e = launch_stage(s2, ctx->plan.fp32, ctx->w_zero, false, true, strm);
+  if (e != hipSuccess) return hip_fail(e, "split-IMEX full step launch");
+  return SDG_OK;
+}
+
+// One step on the set fields in the context's scheme.  SSP-RK3 + Lie: three
+// stages through the two workspace stage buffers, then the column solve back
+// into the state.
 sdg_status enqueue_step(sdg_ctx* ctx, hipStream_t strm) {
+  if (ctx->scheme == SDG_SCHEME_SPLIT_IMEX) return enqueue_imex_step(ctx, strm);
   void* X = ctx->state;
   void* A = ctx->stage_a;
   void* B = ctx->stage_b;
@@ -560,7 +589,7 @@ sdg_status enqueue_step(sdg_ctx* ctx, hipStream_t strm) {
   if ((st = enqueue_stage(ctx, 0, nullptr, X, A, strm)) != SDG_OK) return st;
   if ((st = enqueue_stage(ctx, 1, X, A, B, strm)) != SDG_OK) return st;
   if ((st = enqueue_stage(ctx, 2, X, B, A, strm)) != SDG_OK) return st;
-  return enqueue_solve(ctx, A, X, strm);
+  return enqueue_solve(ctx, A, X, ctx->dt, strm);
 }
 
 }  // namespace
@@ -571,7 +600,7 @@ sdg_status sdg_rhs_3d(sdg_ctx* ctx, const void* dev_T, void* dev_L) {
   if (!dev_T || !dev_L) return fail(SDG_E_ARG, "sdg_rhs_3d: NULL buffer");
   if (dev_T == dev_L) return fail(SDG_E_ARG, "sdg_rhs_3d: output must not alias input");
   DeviceGuard g(ctx->device);
-  StageArgs s = stage_args(ctx, nullptr, dev_T, dev_L, 0.0, 1.0);
+  StageArgs s = stage_args(ctx, nullptr, dev_T, dev_L, 0.0, 1.0, ctx->dt);
   hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, true, false, ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "rhs_3d launch");
   g_err.clear();
@@ -598,7 +627,7 @@ sdg_status sdg_vertical_implicit_solve(sdg_ctx* ctx, const void* dev_Tstar, void
   if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_vertical_implicit_solve needs sdg_set_diffusivity");
   if (!dev_Tstar || !dev_Tout) return fail(SDG_E_ARG, "sdg_vertical_implicit_solve: NULL buffer");
   DeviceGuard g(ctx->device);
-  sdg_status st = enqueue_solve(ctx, dev_Tstar, dev_Tout, ctx->stream);
+  sdg_status st = enqueue_solve(ctx, dev_Tstar, dev_Tout, ctx->dt, ctx->stream);
   if (st == SDG_OK) g_err.clear();
   return st;
 }
@@ -811,6 +840,8 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   sdg_status st = check_explicit(ctx, "sdg_step_adjoint");
   if (st != SDG_OK) return st;
   if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint needs an FP64 context");
+  if (ctx->scheme != SDG_SCHEME_SSPRK3_LIE)
+    return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint reverses the SSP-RK3 + Lie step only");
   if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint needs sdg_set_diffusivity");
   if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint: NULL buffer");
   if (dev_dkappa && !dev_x_next) return fail(SDG_E_ARG, "sdg_step_adjoint: dkappa needs x_next");

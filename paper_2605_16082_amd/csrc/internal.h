@@ -103,6 +103,9 @@ hipError_t launch_column_mass(const DevMesh& m, const void* T, int n_fields, boo
 hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fields,
                              const int32_t* member_off, int n_members, double* out,
                              hipStream_t s);
+// Y <- T0 + Th - 2 Y on live prisms (split-IMEX second-step input).
+hipError_t launch_imex_combine(const DevMesh& m, const void* T0, const void* Th, void* Y, int n_fields, bool fp32,
+                               hipStream_t s);
 hipError_t launch_finite_check(const DevMesh& m, const void* T, int n_fields, bool fp32,
                                int32_t* flag, hipStream_t s);
 

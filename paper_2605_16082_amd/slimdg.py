@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libslimdg.so")
 
 SDG_FP64, SDG_FP32, SDG_FP32_STATE_FP64_SOLVE = 0, 1, 2
 SDG_DV_VU, SDG_DV_VD = 0, 1
+SDG_SCHEME_SSPRK3_LIE, SDG_SCHEME_SPLIT_IMEX = 0, 1
 SDG_DV_MAX_COMP = 4
 STATUS_NAMES = {0: "SDG_OK", -1: "SDG_E_ARG", -2: "SDG_E_MESH", -3: "SDG_E_HIP", -4: "SDG_E_STATE",
                 -5: "SDG_E_UNSUPPORTED", -6: "SDG_E_NUMERIC", -7: "SDG_E_WORKSPACE"}
@@ -81,6 +82,7 @@ class Params(ctypes.Structure):
         ("t_ext", ctypes.c_void_p),
         ("w_is_zero", ctypes.c_int32),
         ("check_finite", ctypes.c_int32),
+        ("time_scheme", ctypes.c_int32),
     ]
 
 
@@ -254,10 +256,11 @@ class SlimDG:
 
     # -- state ---------------------------------------------------------------
     def set_params(self, dt: float, t_ext=None, penalty_eta: float = 4.0, w_is_zero: bool = True,
-                   check_finite: bool = False):
+                   check_finite: bool = False, time_scheme: int = SDG_SCHEME_SSPRK3_LIE):
         text = np.zeros(self.n_fields) if t_ext is None else np.ascontiguousarray(t_ext, dtype=np.float64)
         self._keep["t_ext"] = text
-        p = Params(float(dt), float(penalty_eta), text.ctypes.data, int(bool(w_is_zero)), int(bool(check_finite)))
+        p = Params(float(dt), float(penalty_eta), text.ctypes.data, int(bool(w_is_zero)), int(bool(check_finite)),
+                   int(time_scheme))
         _check(self.lib.sdg_set_params(self.ctx, ctypes.byref(p)))
 
     def set_velocity(self, U):
@@ -370,7 +373,7 @@ class SlimDG:
         return out
 
 
-def from_workload(w, precision: int = SDG_FP64, device: int = 0):
+def from_workload(w, precision: int = SDG_FP64, device: int = 0, time_scheme: int = SDG_SCHEME_SSPRK3_LIE):
     """Upload a workload and set velocity, diffusivity, params and fields."""
     import torch
 
@@ -379,7 +382,7 @@ def from_workload(w, precision: int = SDG_FP64, device: int = 0):
     U = s.scatter(w.U)
     kappa = torch.as_tensor(np.ascontiguousarray(w.kappa, dtype=np.float64)).to(s.device)
     state = s.scatter(w.T0)
-    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero)
+    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, time_scheme=time_scheme)
     s.set_velocity(U)
     s.set_diffusivity(kappa)
     s.set_fields(state)
