@@ -217,6 +217,39 @@ def precision_forms(w, steps, torch, P_mod):
     return out
 
 
+def split_imex_form(w, steps, torch, P_mod):
+    """The two-step split-IMEX scheme against SSP-RK3 + Lie on the benchmark
+    workload, `steps` steps from the same initial state, every context
+    autotuned: time per step, DOF-steps/s (6 P F / step time), the per-field
+    max-norm difference between the schemes in FP64 (their time
+    discretisations differ) and the float-state IMEX error against FP64 IMEX."""
+    P, F = w.n_prisms, w.n_fields
+    out = {"steps": steps}
+    keep = {}
+    for key, prec, scheme in (("lie_fp64", P_mod.SDG_FP64, P_mod.SDG_SCHEME_SSPRK3_LIE),
+                              ("imex_fp64", P_mod.SDG_FP64, P_mod.SDG_SCHEME_SPLIT_IMEX),
+                              ("imex_fp32_state_fp64_solve", P_mod.SDG_FP32_STATE_FP64_SOLVE,
+                               P_mod.SDG_SCHEME_SPLIT_IMEX)):
+        s, U, kappa, x = P_mod.from_workload(w, prec, time_scheme=scheme)
+        tuning = s.autotune(reps=2)
+        s.step(1)
+        s.set_fields(x.copy_(s.scatter(w.T0)))
+        t = event_time(torch, lambda: s.step(steps)) / steps
+        r = {"ms_per_step": t * 1e3, "dof_steps_per_s": 6 * P * F / t,
+             "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))}
+        if key == "imex_fp64":
+            r["max_rel_diff_per_field_vs_lie_fp64"] = field_errors(torch, x, keep["lie_fp64"])
+            r["speedup_vs_lie_fp64"] = out["lie_fp64"]["ms_per_step"] / r["ms_per_step"]
+        elif key == "imex_fp32_state_fp64_solve":
+            r["max_rel_err_per_field_vs_imex_fp64"] = field_errors(torch, x, keep["imex_fp64"])
+        out[key] = r
+        keep[key] = x
+        del s, U, kappa
+    del keep
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_form(torch, P_mod, W, steps, warmup):
     """16 z-level members with 5-60 layers per column in one context: the
     autotuned, graph-captured step in the FP32-state/FP64-solve form against
@@ -375,10 +408,12 @@ def main():
     if not args.no_fp32:
         r32 = run_gpu(w, P_mod.SDG_FP32_STATE_FP64_SOLVE, args.steps, args.warmup, torch, P_mod)
         log("fp32 state / fp64 solve", json.dumps(r32))
-    forms = batched = adjoint = dv = None
+    forms = batched = adjoint = dv = imex = None
     if not args.no_extra:
         dv = column_dv_form(w, torch, P_mod)
         log("column dv", json.dumps(dv))
+        imex = split_imex_form(w, 100, torch, P_mod)
+        log("split imex", json.dumps(imex))
         forms = precision_forms(w, 100, torch, P_mod)
         log("precision forms", json.dumps(forms))
         adjoint = adjoint_form(torch, P_mod, W)
@@ -440,6 +475,8 @@ def main():
         }
     if dv is not None:
         out["column_dv"] = dv
+    if imex is not None:
+        out["split_imex_form"] = imex
     if forms is not None:
         out["precision_forms_after_100_steps"] = forms
     if not args.no_extra:

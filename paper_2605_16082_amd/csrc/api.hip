@@ -554,24 +554,24 @@ sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt,
   return SDG_OK;
 }
 
-// One split-IMEX step (x_0 = X):
-//   A <- y   = x_0 + dt/2 M^-1 R(x_0)          explicit half step (stage, a = 0, b = 1)
-//   B <- x_h = (M - dt/2 A)^-1 M y             vertically implicit half step
-//   A <- x_0 + x_h - 2 y                       (dt M^-1 A x_h = 2 (x_h - y))
-//   X <- A + x_h + dt M^-1 R(x_h)              explicit full step (stage, a = b = 1)
+// One split-IMEX step (x_0 = X), three launches:
+//   A <- y   = x_0 + dt/2 M^-1 R(x_0),  B <- x_0 - 2 y     explicit half step
+//   A <- x_h = (M - dt/2 A)^-1 M y  (in place)            vertically implicit half step
+//   X <- B + 2 (x_h + dt/2 M^-1 R(x_h))                    explicit full step
+// The last line is x_0 + 2 (x_h - y) + dt M^-1 R(x_h), and 2 (x_h - y) is
+// dt M^-1 A x_h by the half step's own system.
 sdg_status enqueue_imex_step(sdg_ctx* ctx, hipStream_t strm) {
   void* X = ctx->state;
   void* A = ctx->stage_a;
   void* B = ctx->stage_b;
   const double h = 0.5 * ctx->dt;
   StageArgs s1 = stage_args(ctx, nullptr, X, A, 0.0, 1.0, h);
+  s1.Tout2 = B;
   hipError_t e = launch_stage(s1, ctx->plan.fp32, ctx->w_zero, false, false, strm);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX half step launch");
-  sdg_status st = enqueue_solve(ctx, A, B, h, strm);
+  sdg_status st = enqueue_solve(ctx, A, A, h, strm);
   if (st != SDG_OK) return st;
-  e = launch_imex_combine(ctx->dm, X, B, A, ctx->plan.F, ctx->plan.fp32, strm);
-  if (e != hipSuccess) return hip_fail(e, "split-IMEX combine launch");
-  StageArgs s2 = stage_args(ctx, A, B, X, 1.0, 1.0, ctx->dt);
+  StageArgs s2 = stage_args(ctx, B, A, X, 1.0, 2.0, h);
   e = launch_stage(s2, ctx->plan.fp32, ctx->w_zero, false, true, strm);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX full step launch");
   return SDG_OK;

@@ -72,6 +72,7 @@ struct StageArgs {
   const void* Tn;      // [F][6][n_slots]
   const void* Ts;
   void* Tout;
+  void* Tout2;         // optional second output Ts - 2 Tout (stage without Tn only)
   const void* U;       // [3][6][n_slots]
   double t_ext[kMaxFields];
   double dt;
@@ -103,9 +104,6 @@ hipError_t launch_column_mass(const DevMesh& m, const void* T, int n_fields, boo
 hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fields,
                              const int32_t* member_off, int n_members, double* out,
                              hipStream_t s);
-// Y <- T0 + Th - 2 Y on live prisms (split-IMEX second-step input).
-hipError_t launch_imex_combine(const DevMesh& m, const void* T0, const void* Th, void* Y, int n_fields, bool fp32,
-                               hipStream_t s);
 hipError_t launch_finite_check(const DevMesh& m, const void* T, int n_fields, bool fp32,
                                int32_t* flag, hipStream_t s);
 

@@ -116,28 +116,6 @@ __global__ __launch_bounds__(64) void finite_kernel(DevMesh m, const R* T, int n
 
 __global__ void clear_kernel(int32_t* flag) { flag[0] = 0; }
 
-// Split-IMEX combination, live prisms only: Y <- T0 + Th - 2 Y, in double.
-// With Y the explicit half step y = x_0 + dt/2 M^-1 R(x_0) and Th its
-// vertically implicit solution x_h, dt M^-1 A x_h = 2 (x_h - y), so the
-// explicit second step x_1 = x_0 + dt M^-1 (R(x_h) + A x_h) is
-// (x_0 + x_h - 2 y) + (x_h + dt M^-1 R(x_h)): this kernel forms the first
-// bracket, an ordinary stage (a = b = 1) adds the second.
-template <typename R>
-__global__ __launch_bounds__(64) void imex_combine_kernel(DevMesh m, const R* T0, const R* Th, R* Y, int nf) {
-  const int cell = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int N = m.nlay[cell * kCell + lane];
-  const size_t SL = (size_t)m.n_slots;
-  const int64_t base = (int64_t)m.cell_base[cell] + lane;
-  for (int l = 0; l < N; ++l) {
-    const int64_t p = base + (int64_t)l * kCell;
-    for (int r = 0; r < 6 * nf; ++r) {
-      const size_t i = (size_t)r * SL + (size_t)p;
-      Y[i] = (R)((double)T0[i] + (double)Th[i] - 2.0 * (double)Y[i]);
-    }
-  }
-}
-
 }  // namespace
 
 hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStream_t s) {
@@ -169,20 +147,6 @@ hipError_t launch_member_sum(const double* col_mass, int n_col_slots, int n_fiel
                              hipStream_t s) {
   hipLaunchKernelGGL(member_sum_kernel, dim3(n_members * n_fields), dim3(256), 0, s, col_mass,
                      n_col_slots, n_fields, member_off, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_imex_combine(const DevMesh& m, const void* T0, const void* Th, void* Y, int n_fields, bool fp32,
-                               hipStream_t s) {
-  if (m.n_cells == 0) return hipSuccess;
-  if (fp32)
-    hipLaunchKernelGGL(imex_combine_kernel<float>, dim3(m.n_cells), dim3(kCell), 0, s, m,
-                       static_cast<const float*>(T0), static_cast<const float*>(Th), static_cast<float*>(Y),
-                       n_fields);
-  else
-    hipLaunchKernelGGL(imex_combine_kernel<double>, dim3(m.n_cells), dim3(kCell), 0, s, m,
-                       static_cast<const double*>(T0), static_cast<const double*>(Th), static_cast<double*>(Y),
-                       n_fields);
   return hipGetLastError();
 }
 

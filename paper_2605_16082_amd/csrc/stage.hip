@@ -427,7 +427,7 @@ __device__ __forceinline__ void minv_factors(const ColGeo<R>& cg, const R dz[3],
 
 // L = M^-1 res (M^-1 = [2 -1; -1 2] (x) Mz^-1), then out = a Tn + b (T + dt L)
 // (or L alone), stored at row f of the output for an active prism.
-template <typename R, bool RHS, bool READ_TN>
+template <typename R, bool RHS, bool READ_TN, bool OUT2>
 __device__ __forceinline__ void finish_field(const StageArgs& a, const MinvF<R>& F, int f, const R T[6],
                                              const R res[6], const R tn[6], uint32_t po, bool active) {
   const R ht[3] = {R(2) * res[0] - res[3], R(2) * res[1] - res[4], R(2) * res[2] - res[5]};
@@ -441,6 +441,7 @@ __device__ __forceinline__ void finish_field(const StageArgs& a, const MinvF<R>&
   L[5] = F.sc * (F.c02 * hb[0] + F.c12 * hb[1] + F.c22 * hb[2]);
   const size_t S = (size_t)a.m.n_slots;
   R* __restrict__ Out = static_cast<R*>(a.Tout);
+  R* __restrict__ Out2 = static_cast<R*>(a.Tout2);
   const R dt = R(a.dt), ca = R(a.a), cb = R(a.b);
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -451,7 +452,11 @@ __device__ __forceinline__ void finish_field(const StageArgs& a, const MinvF<R>&
       out = cb * (T[i] + dt * L[i]);
       if (READ_TN) out += ca * tn[i];
     }
-    if (active) stb(Out + (size_t)(f * 6 + i) * S, po, out);
+    if (active) {
+      stb(Out + (size_t)(f * 6 + i) * S, po, out);
+      // second output T - 2 Tout (the split-IMEX first step)
+      if (OUT2) stb(Out2 + (size_t)(f * 6 + i) * S, po, T[i] - R(2) * out);
+    }
   }
 }
 
@@ -489,7 +494,7 @@ __device__ __forceinline__ TileRange tile_range(const StageArgs& a) {
 // ===========================================================================
 // stage_kernel: one thread per prism.
 // ===========================================================================
-template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN, bool OUT2>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile) {
   const DevMesh& m = a.m;
   const int lane = threadIdx.x & (kCell - 1);
@@ -590,14 +595,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile
     hface_field<R>(bot, te, T + 3, Tx, g);
 #pragma unroll
     for (int n = 0; n < 3; ++n) res[3 + n] += g[n];
-    finish_field<R, RHS, READ_TN>(a, mf, f, T, res, tn, po, active);
+    finish_field<R, RHS, READ_TN, OUT2>(a, mf, f, T, res, tn, po, active);
   }
 }
 
-template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN, bool OUT2>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
   TileRange r = tile_range(a);
-  for (; r.t < r.end; r.t += r.step) stage_tile<R, NF, WZ, RHS, READ_TN>(a, a.tiles[r.t]);
+  for (; r.t < r.end; r.t += r.step) stage_tile<R, NF, WZ, RHS, READ_TN, OUT2>(a, a.tiles[r.t]);
 }
 
 // ===========================================================================
@@ -763,7 +768,7 @@ struct WalkCarry {
 // in order, so each phase issues the loads it needs before the ones needed
 // later: neighbour velocities, then the next layer's copy, then (per field)
 // neighbour traces one field ahead.
-template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN, bool OUT2>
 __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& cg, const LatMeta<R> (&lm)[3],
                                            const WalkCell& wc, int lane, int l, const R* cur, R* nxt,
                                            WalkCarry<R, NF>& cs) {
@@ -868,7 +873,7 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
 #pragma unroll
       for (int i = 0; i < 6; ++i) tn[i] = own(Ly::kTn + f * 6 + i);
     }
-    finish_field<R, RHS, READ_TN>(a, mf, f, T, res, tn, po, active);
+    finish_field<R, RHS, READ_TN, OUT2>(a, mf, f, T, res, tn, po, active);
     if (f + 1 < NF) {
 #pragma unroll
       for (int e = 0; e < 3; ++e)
@@ -882,7 +887,7 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
   for (int v3 = 0; v3 < 3; ++v3) cs.zt[v3] = zb[v3];
 }
 
-template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN, bool OUT2>
 __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
   using Ly = WalkLayout<R, NF, WZ, READ_TN>;
   __shared__ __align__(16) R slot0[Ly::kSlot];
@@ -953,8 +958,8 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
     }
     // layers in pairs so that each half names its slots statically
     for (int l = l0; l < l1; l += 2) {
-      walk_layer<R, NF, WZ, RHS, READ_TN>(a, cg, lm, wc, lane, l, slot0, slot1, cs);
-      if (l + 1 < l1) walk_layer<R, NF, WZ, RHS, READ_TN>(a, cg, lm, wc, lane, l + 1, slot1, slot0, cs);
+      walk_layer<R, NF, WZ, RHS, READ_TN, OUT2>(a, cg, lm, wc, lane, l, slot0, slot1, cs);
+      if (l + 1 < l1) walk_layer<R, NF, WZ, RHS, READ_TN, OUT2>(a, cg, lm, wc, lane, l + 1, slot1, slot0, cs);
     }
     // the last layer may have started a copy into a slot the next tile reuses
     wait_vm();
@@ -980,7 +985,7 @@ hipError_t resident_per_cu(Kern kern, int threads, size_t lds, std::atomic<int>*
   return hipSuccess;
 }
 
-template <typename R, int NF, bool WZ, bool RHS, bool READ_TN>
+template <typename R, int NF, bool WZ, bool RHS, bool READ_TN, bool OUT2>
 hipError_t launch_mode(const StageArgs& a, hipStream_t s) {
   const bool walk = a.tile_layers >= kWalkMinLayers;
   const int threads = walk ? kCell : kCell * a.tile_layers;
@@ -991,8 +996,8 @@ hipError_t launch_mode(const StageArgs& a, hipStream_t s) {
     for (int i = 0; i < kTileChoices; ++i)
       if (kTileLayerOptions[i] == a.tile_layers) ci = i;
     int per_cu = 1;
-    hipError_t e = walk ? resident_per_cu(&walk_kernel<R, NF, WZ, RHS, READ_TN>, threads, 0, &cache[ci], &per_cu)
-                        : resident_per_cu(&stage_kernel<R, NF, WZ, RHS, READ_TN>, threads, 0, &cache[ci], &per_cu);
+    hipError_t e = walk ? resident_per_cu(&walk_kernel<R, NF, WZ, RHS, READ_TN, OUT2>, threads, 0, &cache[ci], &per_cu)
+                        : resident_per_cu(&stage_kernel<R, NF, WZ, RHS, READ_TN, OUT2>, threads, 0, &cache[ci], &per_cu);
     if (e != hipSuccess) return e;
     grid = (per_cu * a.n_cu) & ~7;
     if (grid < 8) grid = 8;
@@ -1000,17 +1005,21 @@ hipError_t launch_mode(const StageArgs& a, hipStream_t s) {
     if (grid > need) grid = need;
   }
   if (walk)
-    hipLaunchKernelGGL((walk_kernel<R, NF, WZ, RHS, READ_TN>), dim3(grid), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((walk_kernel<R, NF, WZ, RHS, READ_TN, OUT2>), dim3(grid), dim3(threads), 0, s, a);
   else
-    hipLaunchKernelGGL((stage_kernel<R, NF, WZ, RHS, READ_TN>), dim3(grid), dim3(threads), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<R, NF, WZ, RHS, READ_TN, OUT2>), dim3(grid), dim3(threads), 0, s, a);
   return hipGetLastError();
 }
 
 template <typename R, int NF>
 hipError_t launch_nf(const StageArgs& a, bool w_zero, bool rhs_only, bool read_tn, hipStream_t s) {
-  if (rhs_only) return w_zero ? launch_mode<R, NF, true, true, false>(a, s) : launch_mode<R, NF, false, true, false>(a, s);
-  if (read_tn) return w_zero ? launch_mode<R, NF, true, false, true>(a, s) : launch_mode<R, NF, false, false, true>(a, s);
-  return w_zero ? launch_mode<R, NF, true, false, false>(a, s) : launch_mode<R, NF, false, false, false>(a, s);
+  if (rhs_only)
+    return w_zero ? launch_mode<R, NF, true, true, false, false>(a, s) : launch_mode<R, NF, false, true, false, false>(a, s);
+  if (read_tn)
+    return w_zero ? launch_mode<R, NF, true, false, true, false>(a, s) : launch_mode<R, NF, false, false, true, false>(a, s);
+  if (a.Tout2)
+    return w_zero ? launch_mode<R, NF, true, false, false, true>(a, s) : launch_mode<R, NF, false, false, false, true>(a, s);
+  return w_zero ? launch_mode<R, NF, true, false, false, false>(a, s) : launch_mode<R, NF, false, false, false, false>(a, s);
 }
 
 template <typename R>
@@ -1029,6 +1038,7 @@ hipError_t launch_r(const StageArgs& a, bool w_zero, bool rhs_only, bool read_tn
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only, bool read_tn,
                         hipStream_t s) {
   if (a.n_tiles == 0) return hipSuccess;
+  if (a.Tout2 && (rhs_only || read_tn)) return hipErrorInvalidValue;
   return fp32 ? launch_r<float>(a, w_zero, rhs_only, read_tn, s)
               : launch_r<double>(a, w_zero, rhs_only, read_tn, s);
 }
