@@ -35,7 +35,9 @@
  *
  * and every nodal array is [component][node 0..5][slot] with n_slots slots
  * (sdg_layout.n_slots).  Slots of padding (l >= nlayers[c], or columns past
- * the last triangle) are never read and never written.  sdg_prism_slots()
+ * the last triangle) of caller arrays are never written, and their values
+ * never reach a result (the column walk copies whole 64-slot rows of a cell,
+ * padding included, and discards the padding lanes).  sdg_prism_slots()
  * returns the slot of every prism in natural order (column by column, layers
  * top to bottom) so callers can scatter and gather.
  *
