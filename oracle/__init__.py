@@ -28,3 +28,4 @@ from .prism_dg import (  # noqa: F401
 )
 from . import column_dv  # noqa: F401,E402
 from . import split_imex  # noqa: F401,E402
+from . import horizontal_diffusion  # noqa: F401,E402

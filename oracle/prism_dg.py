@@ -339,13 +339,18 @@ def advective_residual(mesh: PrismMesh, U, T, t_ext, prisms=None):
     return out
 
 
-def explicit_operator(mesh: PrismMesh, U, T, t_ext, prisms=None):
-    """L(T) = M^-1 R(T), element by element (block-diagonal M, section 2.2)."""
+def explicit_operator(mesh: PrismMesh, U, T, t_ext, prisms=None, kappa_h=None, eta=4.0):
+    """L(T) = M^-1 R(T), element by element (block-diagonal M, section 2.2).
+    With per-column horizontal diffusivities kappa_h, R also holds the
+    horizontal diffusion term (``horizontal_diffusion``)."""
     sel = mesh.all_prisms() if prisms is None else np.asarray(prisms)
     out = np.empty((T.shape[0], 6, len(sel)))
     for i in range(0, len(sel), _CHUNK):
         s = sel[i:i + _CHUNK]
         R = _residual_chunk(mesh, U, T, t_ext, s)          # (F, 6, n)
+        if kappa_h is not None:
+            from .horizontal_diffusion import horizontal_diffusion_term
+            R = R + horizontal_diffusion_term(mesh, kappa_h, T, eta, s)
         M = mass_matrix(mesh, s)                             # (n, 6, 6)
         out[:, :, i:i + _CHUNK] = np.linalg.solve(M, R.transpose(2, 1, 0)).transpose(2, 1, 0)
     return out
@@ -355,11 +360,11 @@ def explicit_operator(mesh: PrismMesh, U, T, t_ext, prisms=None):
 RK3_COEFFS = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
 
 
-def rk_stage(mesh: PrismMesh, U, stage, Tn, Ts, dt, t_ext, prisms=None):
+def rk_stage(mesh: PrismMesh, U, stage, Tn, Ts, dt, t_ext, prisms=None, kappa_h=None, eta=4.0):
     """One explicit SSP-RK3 stage on the selected prisms."""
     sel = mesh.all_prisms() if prisms is None else np.asarray(prisms)
     a, b = RK3_COEFFS[stage]
-    L = explicit_operator(mesh, U, Ts, t_ext, sel)
+    L = explicit_operator(mesh, U, Ts, t_ext, sel, kappa_h, eta)
     return a * Tn[:, :, sel] + b * (Ts[:, :, sel] + dt * L)
 
 
@@ -458,12 +463,12 @@ def implicit_solve(mesh: PrismMesh, kappa, dt, Tstar, eta=4.0, columns=None):
     return out
 
 
-def step(mesh: PrismMesh, U, kappa, T, dt, t_ext, eta=4.0, return_stages=False):
+def step(mesh: PrismMesh, U, kappa, T, dt, t_ext, eta=4.0, return_stages=False, kappa_h=None):
     """Three SSP-RK3 stages of the explicit operator, then one implicit
     vertical-diffusion solve over dt (Lie splitting)."""
-    T1 = rk_stage(mesh, U, 0, T, T, dt, t_ext)
-    T2 = rk_stage(mesh, U, 1, T, T1, dt, t_ext)
-    Ts = rk_stage(mesh, U, 2, T, T2, dt, t_ext)
+    T1 = rk_stage(mesh, U, 0, T, T, dt, t_ext, kappa_h=kappa_h, eta=eta)
+    T2 = rk_stage(mesh, U, 1, T, T1, dt, t_ext, kappa_h=kappa_h, eta=eta)
+    Ts = rk_stage(mesh, U, 2, T, T2, dt, t_ext, kappa_h=kappa_h, eta=eta)
     Tn1 = implicit_solve(mesh, kappa, dt, Ts, eta)
     if return_stages:
         return Tn1, (T1, T2, Ts)

@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .horizontal_diffusion import horizontal_diffusion_term
 from .prism_dg import PrismMesh, _column_masses, advective_residual, vertical_diffusion_matrices
 
 
@@ -56,11 +57,19 @@ def vertical_diffusion_apply(mesh: PrismMesh, kappa, T, eta=4.0):
     return out
 
 
-def imex_step(mesh: PrismMesh, U, kappa, T0, dt, t_ext, eta=4.0, return_half=False):
-    """One split-IMEX step from T0 (F, 6, P); returns T1 (and x_h)."""
+def _residual(mesh, U, T, t_ext, kappa_h, eta):
+    R = advective_residual(mesh, U, T, t_ext)
+    if kappa_h is not None:
+        R = R + horizontal_diffusion_term(mesh, kappa_h, T, eta)
+    return R
+
+
+def imex_step(mesh: PrismMesh, U, kappa, T0, dt, t_ext, eta=4.0, return_half=False, kappa_h=None):
+    """One split-IMEX step from T0 (F, 6, P); returns T1 (and x_h).  With
+    per-column kappa_h, R also holds the (explicit) horizontal diffusion."""
     T0 = np.asarray(T0, dtype=np.float64)
     # step 1: (M - dt/2 A) x_h = M x_0 + dt/2 R(x_0)
-    R0 = advective_residual(mesh, U, T0, t_ext)
+    R0 = _residual(mesh, U, T0, t_ext, kappa_h, eta)
     Th = np.empty_like(T0)
     for _, g, ps in _column_groups(mesh):
         Mc = _column_masses(mesh, g)
@@ -68,7 +77,7 @@ def imex_step(mesh: PrismMesh, U, kappa, T0, dt, t_ext, eta=4.0, return_half=Fal
         rhs = Mc @ _to_columns(T0, ps) + 0.5 * dt * _to_columns(R0, ps)
         _from_columns(np.linalg.solve(Mc - 0.5 * dt * A, rhs), ps, Th)
     # step 2: M x_1 = M x_0 + dt (R(x_h) + A x_h)
-    Rh = advective_residual(mesh, U, Th, t_ext)
+    Rh = _residual(mesh, U, Th, t_ext, kappa_h, eta)
     T1 = np.empty_like(T0)
     for _, g, ps in _column_groups(mesh):
         Mc = _column_masses(mesh, g)
