@@ -72,7 +72,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 4
+#define SDG_ABI_VERSION 5
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -147,6 +147,12 @@ typedef struct {
   int32_t w_is_zero;       /* 1: the vertical velocity component is not read */
   int32_t check_finite;    /* 1: sdg_step checks the state after its last step */
   int32_t time_scheme;     /* sdg_time_scheme of sdg_step (0 = SDG_SCHEME_SSPRK3_LIE) */
+  double okubo_scale;      /* >= 0; 0 = no horizontal diffusion.  Otherwise the explicit
+                              operator also holds the horizontal diffusion of section 1.1
+                              (Okubo diffusivity): along the layers, symmetric interior
+                              penalty on the lateral faces (penalty_eta), zero flux at open
+                              boundaries and walls, per column
+                              kh = okubo_scale * 2.055e-4 * sqrt(J_h)^1.15 m^2/s */
 } sdg_params;
 
 int sdg_abi_version(void);
@@ -196,8 +202,8 @@ sdg_status sdg_set_fields(sdg_ctx* ctx, void* dev_state);
 
 /* dev_L = M^-1 R(dev_T): the horizontal flux operator of section 2.2 in its
  * explicit form (volume term plus upwind lateral and horizontal interface
- * fluxes, block-diagonal mass matrix).  Needs velocity and params.  dev_L
- * must not alias dev_T. */
+ * fluxes, block-diagonal mass matrix), plus the horizontal diffusion when
+ * okubo_scale > 0.  Needs velocity and params.  dev_L must not alias dev_T. */
 sdg_status sdg_rhs_3d(sdg_ctx* ctx, const void* dev_T, void* dev_L);
 
 /* dev_Tout = a dev_Tn + b (dev_Ts + dt L(dev_Ts)) for stage 0, 1, 2 of
@@ -281,8 +287,8 @@ sdg_status sdg_apply_mass(sdg_ctx* ctx, const void* dev_X, void* dev_Y, int inve
  * Synchronises the stream. */
 sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double* host_out);
 
-/* Reverse of one sdg_step (FP64 contexts with SDG_SCHEME_SSPRK3_LIE only,
- * SDG_E_UNSUPPORTED otherwise): not in the paper; it is the
+/* Reverse of one sdg_step (FP64 contexts with SDG_SCHEME_SSPRK3_LIE and no
+ * horizontal diffusion only, SDG_E_UNSUPPORTED otherwise): not in the paper; it is the
  * exact transpose of the section 2.2 stage equations and of the section 2.4
  * column system, in the variable Z = M^-1 lambda where lambda = dJ/dx is the
  * adjoint state:

@@ -47,7 +47,7 @@ struct Plan {
   std::vector<int64_t> zoff;  // per column: first row of its levels in desc.zlev
   int n_tiles[kTileChoices] = {};
   // workspace offsets (bytes)
-  size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_col_member, o_member_off,
+  size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_stage_a, o_stage_b, o_scratch,
       o_colmass, o_msum, o_flag, o_kpart, total;
   size_t state_bytes, velocity_bytes;
@@ -176,6 +176,7 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_nlay = take(sizeof(int32_t) * P.CS);
   P.o_nbr_slot = take(sizeof(int32_t) * 3 * P.CS);
   P.o_nbr_meta = take(sizeof(int32_t) * 3 * P.CS);
+  P.o_nbr_col = take(sizeof(int32_t) * 3 * P.CS);
   P.o_col_member = take(sizeof(int32_t) * P.CS);
   P.o_member_off = take(sizeof(int32_t) * (P.n_members + 1));
   P.o_geo = take(sizeof(double) * kGeoRows * P.CS);
@@ -243,6 +244,7 @@ struct sdg_ctx {
   double t_ext[kMaxFields] = {0, 0, 0, 0};
   bool w_zero = false, check_finite = false;
   int scheme = SDG_SCHEME_SSPRK3_LIE;
+  double kh_scale = 0.0;   // horizontal diffusion off when 0
   const void* U = nullptr;
   const double* kappa = nullptr;
   void* state = nullptr;
@@ -346,7 +348,8 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   DeviceGuard g(ctx->device);
   const int CS = P.CS, C = P.C;
   // host images of the device tables
-  std::vector<int32_t> nlay(CS, 0), nbr_slot(3 * (size_t)CS, -1), nbr_meta(3 * (size_t)CS, 0), colmem(CS, -1);
+  std::vector<int32_t> nlay(CS, 0), nbr_slot(3 * (size_t)CS, -1), nbr_meta(3 * (size_t)CS, 0),
+      nbr_col(3 * (size_t)CS, -1), colmem(CS, -1);
   std::vector<double> xy(6 * (size_t)CS, 0.0), zl(3 * (size_t)P.n_lslots, 0.0);
   std::vector<WgTile> tiles[kTileChoices];
   for (int t = 0; t < kTileChoices; ++t) {
@@ -374,6 +377,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
         if (mesh->tri[3 * c2 + j] == vb && mesh->tri[3 * c2 + (j + 1) % 3] == va) k2 = j;
       nbr_slot[e * (size_t)CS + c] = P.cell_base[c2 / kCell] + c2 % kCell;
       nbr_meta[e * (size_t)CS + c] = (mesh->nlayers[c2] << 2) | k2;
+      nbr_col[e * (size_t)CS + c] = c2;
     }
     const double* z = mesh->zlev + 3 * P.zoff[c];
     for (int lv = 0; lv <= n; ++lv)
@@ -389,6 +393,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
       {P.o_nlay, nlay.data(), sizeof(int32_t) * nlay.size()},
       {P.o_nbr_slot, nbr_slot.data(), sizeof(int32_t) * nbr_slot.size()},
       {P.o_nbr_meta, nbr_meta.data(), sizeof(int32_t) * nbr_meta.size()},
+      {P.o_nbr_col, nbr_col.data(), sizeof(int32_t) * nbr_col.size()},
       {P.o_col_member, colmem.data(), sizeof(int32_t) * colmem.size()},
       {P.o_member_off, P.member_off.data(), sizeof(int32_t) * P.member_off.size()},
       {P.o_xy, xy.data(), sizeof(double) * xy.size()},
@@ -418,6 +423,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   dm.nlay = reinterpret_cast<const int32_t*>(ws + P.o_nlay);
   dm.nbr_slot = reinterpret_cast<const int32_t*>(ws + P.o_nbr_slot);
   dm.nbr_meta = reinterpret_cast<const int32_t*>(ws + P.o_nbr_meta);
+  dm.nbr_col = reinterpret_cast<const int32_t*>(ws + P.o_nbr_col);
   dm.geo = reinterpret_cast<const double*>(ws + P.o_geo);
   dm.geo32 = reinterpret_cast<const float*>(ws + P.o_geo32);
   dm.zl = reinterpret_cast<const double*>(ws + P.o_zl);
@@ -460,7 +466,10 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
   }
   if (p->time_scheme != SDG_SCHEME_SSPRK3_LIE && p->time_scheme != SDG_SCHEME_SPLIT_IMEX)
     return fail(SDG_E_ARG, "unknown time_scheme %d", p->time_scheme);
+  if (!(p->okubo_scale >= 0.0) || !std::isfinite(p->okubo_scale))
+    return fail(SDG_E_ARG, "okubo_scale must be finite and >= 0 (got %g)", p->okubo_scale);
   ctx->scheme = p->time_scheme;
+  ctx->kh_scale = p->okubo_scale;
   ctx->dt = p->dt;
   ctx->eta = eta;
   ctx->w_zero = p->w_is_zero != 0;
@@ -529,12 +538,31 @@ StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, d
   return s;
 }
 
+// The horizontal diffusion part of a stage whose explicit operator was just
+// applied by the stage kernel: Tout += c1 M^-1 D(Ts) (Tout2 += c2 M^-1 D(Ts)).
+hipError_t hdiff_after_stage(sdg_ctx* ctx, const StageArgs& s, double c1, double c2, hipStream_t strm) {
+  if (!(ctx->kh_scale > 0.0)) return hipSuccess;
+  HdiffArgs h{};
+  h.m = ctx->dm;
+  h.n_fields = ctx->plan.F;
+  h.Ts = s.Ts;
+  h.Tout = s.Tout;
+  h.Tout2 = s.Tout2;
+  h.c1 = c1;
+  h.c2 = c2;
+  // Okubo: K = 0.0103 l^1.15 cm^2/s with l in cm, i.e. 0.0103 100^1.15 1e-4 l^1.15 m^2/s in metres
+  h.kh_coef = ctx->kh_scale * 0.0103 * std::pow(100.0, 1.15) * 1.0e-4;
+  h.eta = ctx->eta;
+  return launch_hdiff(h, ctx->plan.fp32, strm);
+}
+
 constexpr double kRk[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
 
 sdg_status enqueue_stage(sdg_ctx* ctx, int stage, const void* Tn, const void* Ts, void* Tout,
                          hipStream_t strm) {
   StageArgs s = stage_args(ctx, Tn, Ts, Tout, kRk[stage][0], kRk[stage][1], ctx->dt);
   hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, false, stage > 0, strm);
+  if (e == hipSuccess) e = hdiff_after_stage(ctx, s, kRk[stage][1] * ctx->dt, 0.0, strm);
   if (e != hipSuccess) return hip_fail(e, "rk_stage launch");
   return SDG_OK;
 }
@@ -568,11 +596,13 @@ sdg_status enqueue_imex_step(sdg_ctx* ctx, hipStream_t strm) {
   StageArgs s1 = stage_args(ctx, nullptr, X, A, 0.0, 1.0, h);
   s1.Tout2 = B;
   hipError_t e = launch_stage(s1, ctx->plan.fp32, ctx->w_zero, false, false, strm);
+  if (e == hipSuccess) e = hdiff_after_stage(ctx, s1, h, -2.0 * h, strm);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX half step launch");
   sdg_status st = enqueue_solve(ctx, A, A, h, strm);
   if (st != SDG_OK) return st;
   StageArgs s2 = stage_args(ctx, B, A, X, 1.0, 2.0, h);
   e = launch_stage(s2, ctx->plan.fp32, ctx->w_zero, false, true, strm);
+  if (e == hipSuccess) e = hdiff_after_stage(ctx, s2, 2.0 * h, 0.0, strm);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX full step launch");
   return SDG_OK;
 }
@@ -602,6 +632,7 @@ sdg_status sdg_rhs_3d(sdg_ctx* ctx, const void* dev_T, void* dev_L) {
   DeviceGuard g(ctx->device);
   StageArgs s = stage_args(ctx, nullptr, dev_T, dev_L, 0.0, 1.0, ctx->dt);
   hipError_t e = launch_stage(s, ctx->plan.fp32, ctx->w_zero, true, false, ctx->stream);
+  if (e == hipSuccess) e = hdiff_after_stage(ctx, s, 1.0, 0.0, ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "rhs_3d launch");
   g_err.clear();
   return SDG_OK;
@@ -842,6 +873,8 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint needs an FP64 context");
   if (ctx->scheme != SDG_SCHEME_SSPRK3_LIE)
     return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint reverses the SSP-RK3 + Lie step only");
+  if (ctx->kh_scale > 0.0)
+    return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint does not include horizontal diffusion");
   if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint needs sdg_set_diffusivity");
   if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint: NULL buffer");
   if (dev_dkappa && !dev_x_next) return fail(SDG_E_ARG, "sdg_step_adjoint: dkappa needs x_next");

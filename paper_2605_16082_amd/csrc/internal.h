@@ -39,6 +39,7 @@ struct DevMesh {
   const int32_t* nlay;         // [n_col_slots], 0 on padding columns
   const int32_t* nbr_slot;     // [3][n_col_slots]: prism slot of the neighbour's layer 0, or -1
   const int32_t* nbr_meta;     // [3][n_col_slots]: (neighbour nlayers << 2) | neighbour edge
+  const int32_t* nbr_col;      // [3][n_col_slots]: neighbour column slot, or -1
   const double* geo;           // [kGeoRows][n_col_slots]
   const float* geo32;          // same, float
   const double* zl;            // [3][n_lslots] level heights
@@ -90,7 +91,20 @@ struct SolveArgs {
   double eta;
 };
 
+// Horizontal diffusion: Tout += c1 M^-1 D(Ts) (and Tout2 += c2 M^-1 D(Ts)).
+struct HdiffArgs {
+  DevMesh m;
+  int32_t n_fields;
+  const void* Ts;
+  void* Tout;
+  void* Tout2;         // optional
+  double c1, c2;
+  double kh_coef;      // kh = kh_coef * sqrt(J_h)^1.15 per column
+  double eta;
+};
+
 // Kernel launchers (defined next to their kernels).
+hipError_t launch_hdiff(const HdiffArgs& a, bool fp32, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStream_t s);
 hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,

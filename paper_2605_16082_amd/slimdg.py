@@ -83,6 +83,7 @@ class Params(ctypes.Structure):
         ("w_is_zero", ctypes.c_int32),
         ("check_finite", ctypes.c_int32),
         ("time_scheme", ctypes.c_int32),
+        ("okubo_scale", ctypes.c_double),
     ]
 
 
@@ -256,11 +257,12 @@ class SlimDG:
 
     # -- state ---------------------------------------------------------------
     def set_params(self, dt: float, t_ext=None, penalty_eta: float = 4.0, w_is_zero: bool = True,
-                   check_finite: bool = False, time_scheme: int = SDG_SCHEME_SSPRK3_LIE):
+                   check_finite: bool = False, time_scheme: int = SDG_SCHEME_SSPRK3_LIE,
+                   okubo_scale: float = 0.0):
         text = np.zeros(self.n_fields) if t_ext is None else np.ascontiguousarray(t_ext, dtype=np.float64)
         self._keep["t_ext"] = text
         p = Params(float(dt), float(penalty_eta), text.ctypes.data, int(bool(w_is_zero)), int(bool(check_finite)),
-                   int(time_scheme))
+                   int(time_scheme), float(okubo_scale))
         _check(self.lib.sdg_set_params(self.ctx, ctypes.byref(p)))
 
     def set_velocity(self, U):
@@ -373,7 +375,8 @@ class SlimDG:
         return out
 
 
-def from_workload(w, precision: int = SDG_FP64, device: int = 0, time_scheme: int = SDG_SCHEME_SSPRK3_LIE):
+def from_workload(w, precision: int = SDG_FP64, device: int = 0, time_scheme: int = SDG_SCHEME_SSPRK3_LIE,
+                  okubo_scale: float = 0.0):
     """Upload a workload and set velocity, diffusivity, params and fields."""
     import torch
 
@@ -382,7 +385,7 @@ def from_workload(w, precision: int = SDG_FP64, device: int = 0, time_scheme: in
     U = s.scatter(w.U)
     kappa = torch.as_tensor(np.ascontiguousarray(w.kappa, dtype=np.float64)).to(s.device)
     state = s.scatter(w.T0)
-    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, time_scheme=time_scheme)
+    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, time_scheme=time_scheme, okubo_scale=okubo_scale)
     s.set_velocity(U)
     s.set_diffusivity(kappa)
     s.set_fields(state)
