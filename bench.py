@@ -250,6 +250,37 @@ def split_imex_form(w, steps, torch, P_mod):
     return out
 
 
+def hdiff_form(w, steps, torch, P_mod, reps=10):
+    """Horizontal (Okubo) diffusion on the benchmark workload in FP64: step
+    time with and without it (SSP-RK3 + Lie, autotuned), and the hdiff
+    kernel's own time as rhs_3d with it minus rhs_3d without it.  Algorithmic
+    bytes of one hdiff launch: the stage input read once, the stage output
+    read and written (18 values per prism and field), plus per column the
+    geometry of the column and its three neighbours (11 values and 3 indices
+    each)."""
+    P, C, F = w.n_prisms, w.n_cols, w.n_fields
+    s, U, kappa, x = P_mod.from_workload(w, P_mod.SDG_FP64, okubo_scale=1.0)
+    tuning = s.autotune(reps=2)
+    s.step(1)
+    s.set_fields(x.copy_(s.scatter(w.T0)))
+    t_on = event_time(torch, lambda: s.step(steps)) / steps
+    out_buf = s.new_state()
+    t_rhs_on = time_calls(torch, lambda: s.rhs_3d(x, out_buf), reps)
+    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, okubo_scale=0.0)
+    t_rhs_off = time_calls(torch, lambda: s.rhs_3d(x, out_buf), reps)
+    s.set_fields(x.copy_(s.scatter(w.T0)))
+    t_off = event_time(torch, lambda: s.step(steps)) / steps
+    t_k = t_rhs_on - t_rhs_off
+    by = 18 * F * P * 8 + C * (4 * 11 * 8 + 3 * 3 * 4)
+    res = {"ms_per_step_with": t_on * 1e3, "ms_per_step_without": t_off * 1e3,
+           "hdiff_kernel_ms": t_k * 1e3, "hdiff_bytes_per_launch": int(by),
+           "hdiff_GBps": by / t_k / 1e9, "hdiff_frac": by / t_k / HBM_PEAK,
+           "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))}
+    del s, U, kappa, x, out_buf
+    torch.cuda.empty_cache()
+    return res
+
+
 def batched_form(torch, P_mod, W, steps, warmup):
     """16 z-level members with 5-60 layers per column in one context: the
     autotuned, graph-captured step in the FP32-state/FP64-solve form against
@@ -373,6 +404,8 @@ def main():
                     help="skip the precision-form, batched and adjoint measurements")
     ap.add_argument("--column-dv-only", action="store_true",
                     help="time only the matrix-free column solves and print their JSON")
+    ap.add_argument("--hdiff-only", action="store_true",
+                    help="time only the horizontal diffusion form and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device twice (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -402,18 +435,23 @@ def main():
     if args.column_dv_only:
         print(json.dumps({"column_dv": column_dv_form(w, torch, P_mod)}), flush=True)
         return
+    if args.hdiff_only:
+        print(json.dumps({"hdiff_form": hdiff_form(w, 10, torch, P_mod)}), flush=True)
+        return
     r64 = run_gpu(w, P_mod.SDG_FP64, args.steps, args.warmup, torch, P_mod)
     log("fp64", json.dumps(r64))
     r32 = None
     if not args.no_fp32:
         r32 = run_gpu(w, P_mod.SDG_FP32_STATE_FP64_SOLVE, args.steps, args.warmup, torch, P_mod)
         log("fp32 state / fp64 solve", json.dumps(r32))
-    forms = batched = adjoint = dv = imex = None
+    forms = batched = adjoint = dv = imex = hd = None
     if not args.no_extra:
         dv = column_dv_form(w, torch, P_mod)
         log("column dv", json.dumps(dv))
         imex = split_imex_form(w, 100, torch, P_mod)
         log("split imex", json.dumps(imex))
+        hd = hdiff_form(w, 20, torch, P_mod)
+        log("hdiff", json.dumps(hd))
         forms = precision_forms(w, 100, torch, P_mod)
         log("precision forms", json.dumps(forms))
         adjoint = adjoint_form(torch, P_mod, W)
@@ -477,6 +515,8 @@ def main():
         out["column_dv"] = dv
     if imex is not None:
         out["split_imex_form"] = imex
+    if hd is not None:
+        out["hdiff_form"] = hd
     if forms is not None:
         out["precision_forms_after_100_steps"] = forms
     if not args.no_extra:

@@ -49,7 +49,7 @@ struct Plan {
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_stage_a, o_stage_b, o_scratch,
-      o_colmass, o_msum, o_flag, o_kpart, total;
+      o_colmass, o_msum, o_flag, o_kpart, o_kh, total;
   size_t state_bytes, velocity_bytes;
 };
 
@@ -192,6 +192,7 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_msum = take(sizeof(double) * (size_t)P.F * P.n_members);
   P.o_flag = take(sizeof(int32_t) * 64);
   P.o_kpart = take(sizeof(double) * (size_t)P.max_layers * (size_t)P.n_cells);
+  P.o_kh = take(sizeof(double) * (size_t)P.CS);
   P.total = o;
   return SDG_OK;
 }
@@ -235,6 +236,7 @@ struct sdg_ctx {
   double* msum = nullptr;
   int32_t* flag = nullptr;
   double* kpart = nullptr;
+  double* kh = nullptr;     // per-column horizontal diffusivity (workspace)
   void* stage_a = nullptr;
   void* stage_b = nullptr;
   double* scratch = nullptr;
@@ -445,6 +447,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   ctx->msum = reinterpret_cast<double*>(ws + Q.o_msum);
   ctx->flag = reinterpret_cast<int32_t*>(ws + Q.o_flag);
   ctx->kpart = reinterpret_cast<double*>(ws + Q.o_kpart);
+  ctx->kh = reinterpret_cast<double*>(ws + Q.o_kh);
   ctx->stage_a = ws + Q.o_stage_a;
   ctx->stage_b = ws + Q.o_stage_b;
   ctx->scratch = reinterpret_cast<double*>(ws + Q.o_scratch);
@@ -459,15 +462,24 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
   if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(SDG_E_ARG, "dt must be finite and > 0 (got %g)", p->dt);
   const double eta = p->penalty_eta > 0.0 ? p->penalty_eta : 4.0;
   if (!std::isfinite(eta)) return fail(SDG_E_ARG, "penalty_eta must be finite");
+  double text[kMaxFields] = {};
   for (int f = 0; f < ctx->plan.F; ++f) {
     const double v = p->t_ext ? p->t_ext[f] : 0.0;
     if (!std::isfinite(v)) return fail(SDG_E_ARG, "t_ext[%d] is not finite", f);
-    ctx->t_ext[f] = v;
+    text[f] = v;
   }
   if (p->time_scheme != SDG_SCHEME_SSPRK3_LIE && p->time_scheme != SDG_SCHEME_SPLIT_IMEX)
     return fail(SDG_E_ARG, "unknown time_scheme %d", p->time_scheme);
   if (!(p->okubo_scale >= 0.0) || !std::isfinite(p->okubo_scale))
     return fail(SDG_E_ARG, "okubo_scale must be finite and >= 0 (got %g)", p->okubo_scale);
+  if (p->okubo_scale > 0.0) {
+    // Okubo: K = 0.0103 l^1.15 cm^2/s with l in cm = 0.0103 100^1.15 1e-4 l^1.15 m^2/s, l in m
+    DeviceGuard g(ctx->device);
+    const double coef = p->okubo_scale * 0.0103 * std::pow(100.0, 1.15) * 1.0e-4;
+    hipError_t e = launch_okubo(ctx->dm, coef, ctx->kh, ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "horizontal diffusivity launch");
+  }
+  for (int f = 0; f < ctx->plan.F; ++f) ctx->t_ext[f] = text[f];
   ctx->scheme = p->time_scheme;
   ctx->kh_scale = p->okubo_scale;
   ctx->dt = p->dt;
@@ -544,14 +556,16 @@ hipError_t hdiff_after_stage(sdg_ctx* ctx, const StageArgs& s, double c1, double
   if (!(ctx->kh_scale > 0.0)) return hipSuccess;
   HdiffArgs h{};
   h.m = ctx->dm;
+  h.tiles = ctx->tiles[1];
+  h.n_tiles = ctx->plan.n_tiles[1];
+  h.tile_layers = kTileLayerOptions[1];
   h.n_fields = ctx->plan.F;
   h.Ts = s.Ts;
   h.Tout = s.Tout;
   h.Tout2 = s.Tout2;
   h.c1 = c1;
   h.c2 = c2;
-  // Okubo: K = 0.0103 l^1.15 cm^2/s with l in cm, i.e. 0.0103 100^1.15 1e-4 l^1.15 m^2/s in metres
-  h.kh_coef = ctx->kh_scale * 0.0103 * std::pow(100.0, 1.15) * 1.0e-4;
+  h.kh = ctx->kh;
   h.eta = ctx->eta;
   return launch_hdiff(h, ctx->plan.fp32, strm);
 }

@@ -16,8 +16,10 @@
 // with g = sum_a grad(lambda_a) T_a of the face's three nodes; the face
 // measure is |e| z_zeta(s) ds dzeta with z_zeta linear along the edge.  The
 // kernel adds c1 M^-1 D to Tout (and c2 M^-1 D to Tout2), after the stage
-// kernel has written them: one wavefront per cell, one lane per column, a walk
-// down the layers.
+// kernel has written them, one thread per prism over tiles of two layers of a
+// cell (128 threads): the per-column factors are cheap to rebuild, and the
+// many independent prisms keep enough loads in flight.  kh is computed once
+// per column (okubo_kernel) when the parameters are set.
 #include "internal.h"
 
 namespace sdg {
@@ -45,10 +47,11 @@ __device__ __forceinline__ void lambda_grads(const R* geo, int CS, int c, R gl[3
   gl[0][1] = -(gl[1][1] + gl[2][1]);
 }
 
-// kh = coef sqrt(J_h)^1.15, coef = okubo_scale * (Okubo's constant in metres)
-template <typename R>
-__device__ __forceinline__ R okubo(R Jh, double coef) {
-  return R(coef * pow((double)Jh, 0.575));
+// kh[c] = coef sqrt(J_h)^1.15, coef = okubo_scale * (Okubo's constant in metres)
+__global__ __launch_bounds__(256) void okubo_kernel(DevMesh m, double coef, double* kh) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m.n_col_slots) return;
+  kh[c] = m.nlay[c] > 0 ? coef * pow(m.geo[G_JH * m.n_col_slots + c], 0.575) : 0.0;
 }
 
 // Field-independent data of one lateral face of a column.
@@ -60,14 +63,17 @@ struct HFace {
   R dn[3], dnn[3];           // n . grad(lambda) of the own and the neighbour's basis
 };
 
+constexpr int kHdiffLayers = 2;   // layers per workgroup (the 2-layer tile table)
+
 template <typename R, int NF, bool OUT2>
-__global__ __launch_bounds__(64) void hdiff_kernel(HdiffArgs a) {
+__global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a) {
   const DevMesh& m = a.m;
-  const int cell = blockIdx.x;
-  const int lane = threadIdx.x;
+  const WgTile tile = a.tiles[blockIdx.x];
+  const int lane = threadIdx.x % kCell;
+  const int l = tile.layer0 + threadIdx.x / kCell;
+  const int cell = tile.cell;
   const int c = cell * kCell + lane;
-  const int N = m.nlay[c];
-  if (N == 0) return;
+  if (l >= m.nlay[c]) return;
   const int CS = m.n_col_slots;
   const size_t S = (size_t)m.n_slots, LS = (size_t)m.n_lslots;
   const R* geo = geo_rows<R>(m);
@@ -79,7 +85,7 @@ __global__ __launch_bounds__(64) void hdiff_kernel(HdiffArgs a) {
 
   R gl[3][2], Jh;
   lambda_grads<R>(geo, CS, c, gl, Jh);
-  const R kh = okubo<R>(Jh, a.kh_coef);
+  const R kh = R(a.kh[c]);
 
   HFace<R> fc[3];
 #pragma unroll
@@ -104,27 +110,19 @@ __global__ __launch_bounds__(64) void hdiff_kernel(HdiffArgs a) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) gn[j][0] = gn[j][1] = R(0);
     }
-    F.khn = F.interior ? okubo<R>(Jn, a.kh_coef) : R(0);
+    F.khn = F.interior ? R(a.kh[ncol]) : R(0);
 #pragma unroll
     for (int j = 0; j < 3; ++j) F.dnn[j] = nx * gn[j][0] + ny * gn[j][1];
     const R h = (Jh < Jn ? Jh : Jn) / F.Le;
     F.sig = eta * R(0.5) * (kh + F.khn) / h;
   }
 
-  const int64_t base = (int64_t)m.cell_base[cell] + lane;
-  const int64_t lbase = (int64_t)m.cell_lbase[cell] + lane;
-  R zt[3];
+  const int64_t p = (int64_t)m.cell_base[cell] + lane + (int64_t)l * kCell;
+  const int64_t lt = (int64_t)m.cell_lbase[cell] + lane + (int64_t)l * kCell;
+  {
+    R dz[3];
 #pragma unroll
-  for (int v = 0; v < 3; ++v) zt[v] = zl[v * LS + (size_t)lbase];
-  for (int l = 0; l < N; ++l) {
-    const int64_t p = base + (int64_t)l * kCell;
-    R zb[3], dz[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-      zb[v] = zl[v * LS + (size_t)(lbase + (int64_t)(l + 1) * kCell)];
-      dz[v] = zt[v] - zb[v];
-      zt[v] = zb[v];
-    }
+    for (int v = 0; v < 3; ++v) dz[v] = zl[v * LS + (size_t)lt] - zl[v * LS + (size_t)(lt + kCell)];
     // volume factor kh int_K z_zeta J_h dxi deta = kh J_h (dz_0 + dz_1 + dz_2) / 12
     const R vf = kh * Jh * (dz[0] + dz[1] + dz[2]) * R(1.0 / 12.0);
     // Mz^-1 = sc * cofactors of m (Mz = J_h/120 m), M^-1 = [2 -1; -1 2] (x) Mz^-1
@@ -225,7 +223,7 @@ __global__ __launch_bounds__(64) void hdiff_kernel(HdiffArgs a) {
 
 template <typename R, bool OUT2>
 hipError_t launch_nf(const HdiffArgs& a, hipStream_t s) {
-  const dim3 grid(a.m.n_cells), block(kCell);
+  const dim3 grid(a.n_tiles), block(kCell * kHdiffLayers);
   switch (a.n_fields) {
     case 1: hipLaunchKernelGGL((hdiff_kernel<R, 1, OUT2>), grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL((hdiff_kernel<R, 2, OUT2>), grid, block, 0, s, a); break;
@@ -238,8 +236,16 @@ hipError_t launch_nf(const HdiffArgs& a, hipStream_t s) {
 
 }  // namespace
 
+hipError_t launch_okubo(const DevMesh& m, double coef, double* kh, hipStream_t s) {
+  const int n = m.n_col_slots;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(okubo_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, coef, kh);
+  return hipGetLastError();
+}
+
 hipError_t launch_hdiff(const HdiffArgs& a, bool fp32, hipStream_t s) {
-  if (a.m.n_cells == 0) return hipSuccess;
+  if (a.n_tiles == 0) return hipSuccess;
+  if (a.tile_layers != kHdiffLayers) return hipErrorInvalidValue;
   const bool out2 = a.Tout2 != nullptr;
   if (fp32) return out2 ? launch_nf<float, true>(a, s) : launch_nf<float, false>(a, s);
   return out2 ? launch_nf<double, true>(a, s) : launch_nf<double, false>(a, s);

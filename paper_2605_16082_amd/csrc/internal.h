@@ -94,17 +94,22 @@ struct SolveArgs {
 // Horizontal diffusion: Tout += c1 M^-1 D(Ts) (and Tout2 += c2 M^-1 D(Ts)).
 struct HdiffArgs {
   DevMesh m;
+  const WgTile* tiles;   // the 2-layer tile table
+  int32_t n_tiles;
+  int32_t tile_layers;   // 2
   int32_t n_fields;
   const void* Ts;
   void* Tout;
-  void* Tout2;         // optional
+  void* Tout2;           // optional
   double c1, c2;
-  double kh_coef;      // kh = kh_coef * sqrt(J_h)^1.15 per column
+  const double* kh;      // [n_col_slots] horizontal diffusivity per column
   double eta;
 };
 
 // Kernel launchers (defined next to their kernels).
 hipError_t launch_hdiff(const HdiffArgs& a, bool fp32, hipStream_t s);
+// kh[c] = coef * sqrt(J_h)^1.15 for every live column.
+hipError_t launch_okubo(const DevMesh& m, double coef, double* kh, hipStream_t s);
 hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStream_t s);
 hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,
