@@ -287,15 +287,16 @@ sdg_status sdg_apply_mass(sdg_ctx* ctx, const void* dev_X, void* dev_Y, int inve
  * Synchronises the stream. */
 sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double* host_out);
 
-/* Reverse of one sdg_step (FP64 contexts with SDG_SCHEME_SSPRK3_LIE and no
- * horizontal diffusion only, SDG_E_UNSUPPORTED otherwise): not in the paper; it is the
+/* Reverse of one sdg_step (FP64 contexts with SDG_SCHEME_SSPRK3_LIE only,
+ * SDG_E_UNSUPPORTED otherwise): not in the paper; it is the
  * exact transpose of the section 2.2 stage equations and of the section 2.4
  * column system, in the variable Z = M^-1 lambda where lambda = dJ/dx is the
  * adjoint state:
  *   mu     = (M - dt A^T)^-1 M Z^{n+1}                     (transposed column solve)
  *   dkappa[l] += dt mu^T (dA/dkappa_l) x^{n+1}              (if dev_dkappa != NULL)
  *   Z^n    = reverse SSP-RK3 stages with M^-1 R_lin^T       (R_lin: the advective
- *            residual without the exterior inflow values)
+ *            residual without the exterior inflow values, plus the
+ *            horizontal diffusion D when okubo_scale > 0, D^T = D)
  * so that lambda^n = M Z^n.  dev_z_next, dev_z_out: [n_fields][6][n_slots]
  * doubles (may alias); dev_x_next: the state after the forward step being
  * reversed; dev_dkappa: [max_layers] doubles, accumulated.  Uses the

@@ -175,21 +175,26 @@ def objective(mesh: PrismMesh, T) -> float:
     return float(np.sqrt(np.sum(x * (M @ x))))
 
 
-def forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0):
+def forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
     """States x^0 .. x^N of the matrix-free oracle step."""
     xs = [np.array(T0, dtype=np.float64)]
     for _ in range(n_steps):
-        xs.append(step(mesh, U, kappa, xs[-1], dt, t_ext, eta))
+        xs.append(step(mesh, U, kappa, xs[-1], dt, t_ext, eta, kappa_h=kappa_h))
     return xs
 
 
-def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0):
-    """(J, dJ/dT0 of shape (F, 6, P), dJ/dkappa of shape (len(kappa),))."""
+def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
+    """(J, dJ/dT0 of shape (F, 6, P), dJ/dkappa of shape (len(kappa),)).
+    With per-column kappa_h the explicit operator also holds the horizontal
+    diffusion matrix D (linear, so it adds D to R_lin)."""
     kappa = np.asarray(kappa, dtype=np.float64)
     F = T0.shape[0]
-    xs = forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta)
+    xs = forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta, kappa_h)
     M = mass_matrix_global(mesh)
     R = advection_matrix(mesh, U)
+    if kappa_h is not None:
+        from .horizontal_diffusion import horizontal_diffusion_matrix
+        R = (R + horizontal_diffusion_matrix(mesh, kappa_h, eta)).tocsr()
     Minv_R = sp.csr_matrix(spla.spsolve(M.tocsc(), R.tocsc()))
     Lt = Minv_R.T.tocsr()                                   # L^T
     A = vertical_matrix_global(mesh, kappa, eta)

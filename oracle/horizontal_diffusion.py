@@ -127,3 +127,19 @@ def horizontal_diffusion_term(mesh: PrismMesh, kappa_h, T, eta=4.0, prisms=None)
                     phi_in[None, :, None] * (avg - sigma[None, :] * jump)[:, None, :]
                     + 0.5 * kh[None, None, :] * dphin.T[None] * jump[:, None, :])
     return out
+
+
+def horizontal_diffusion_matrix(mesh: PrismMesh, kappa_h, eta=4.0, chunk=512):
+    """D (6P x 6P), degrees of freedom numbered 6 p + i (prism p, node i),
+    assembled column by column from the matrix-free term applied to unit
+    vectors; practical on small meshes only."""
+    import scipy.sparse as sp
+    n = 6 * mesh.P
+    cols = []
+    for d0 in range(0, n, chunk):
+        d = np.arange(d0, min(n, d0 + chunk))
+        E = np.zeros((len(d), 6, mesh.P))
+        E[np.arange(len(d)), d % 6, d // 6] = 1.0
+        out = horizontal_diffusion_term(mesh, kappa_h, E, eta)       # (k, 6, P)
+        cols.append(sp.csr_matrix(out.transpose(0, 2, 1).reshape(len(d), n)))
+    return sp.vstack(cols).T.tocsr()

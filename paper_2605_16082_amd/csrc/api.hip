@@ -550,9 +550,11 @@ StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, d
   return s;
 }
 
-// The horizontal diffusion part of a stage whose explicit operator was just
-// applied by the stage kernel: Tout += c1 M^-1 D(Ts) (Tout2 += c2 M^-1 D(Ts)).
-hipError_t hdiff_after_stage(sdg_ctx* ctx, const StageArgs& s, double c1, double c2, hipStream_t strm) {
+// The horizontal diffusion part of an explicit stage (forward or adjoint)
+// whose other terms were just written: Tout += c1 M^-1 D(Ts) (and
+// Tout2 += c2 M^-1 D(Ts)).  No launch when horizontal diffusion is off.
+hipError_t enqueue_hdiff(sdg_ctx* ctx, const void* Ts, void* Tout, void* Tout2, double c1, double c2,
+                         hipStream_t strm) {
   if (!(ctx->kh_scale > 0.0)) return hipSuccess;
   HdiffArgs h{};
   h.m = ctx->dm;
@@ -560,14 +562,18 @@ hipError_t hdiff_after_stage(sdg_ctx* ctx, const StageArgs& s, double c1, double
   h.n_tiles = ctx->plan.n_tiles[1];
   h.tile_layers = kTileLayerOptions[1];
   h.n_fields = ctx->plan.F;
-  h.Ts = s.Ts;
-  h.Tout = s.Tout;
-  h.Tout2 = s.Tout2;
+  h.Ts = Ts;
+  h.Tout = Tout;
+  h.Tout2 = Tout2;
   h.c1 = c1;
   h.c2 = c2;
   h.kh = ctx->kh;
   h.eta = ctx->eta;
   return launch_hdiff(h, ctx->plan.fp32, strm);
+}
+
+hipError_t hdiff_after_stage(sdg_ctx* ctx, const StageArgs& s, double c1, double c2, hipStream_t strm) {
+  return enqueue_hdiff(ctx, s.Ts, s.Tout, s.Tout2, c1, c2, strm);
 }
 
 constexpr double kRk[3][2] = {{0.0, 1.0}, {0.75, 0.25}, {1.0 / 3.0, 2.0 / 3.0}};
@@ -887,8 +893,6 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint needs an FP64 context");
   if (ctx->scheme != SDG_SCHEME_SSPRK3_LIE)
     return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint reverses the SSP-RK3 + Lie step only");
-  if (ctx->kh_scale > 0.0)
-    return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint does not include horizontal diffusion");
   if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint needs sdg_set_diffusivity");
   if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint: NULL buffer");
   if (dev_dkappa && !dev_x_next) return fail(SDG_E_ARG, "sdg_step_adjoint: dkappa needs x_next");
@@ -915,14 +919,20 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
     if (e != hipSuccess) return hip_fail(e, "kappa gradient launch");
   }
   const bool wz = ctx->w_zero;
-  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, mu, nullptr, nullptr, zb2, U, ctx->dt,
+  // the horizontal diffusion D is symmetric, so its part of M^-1 (R_lin + D)^T
+  // is M^-1 D, added to each stage as in the forward step
+  const double dt = ctx->dt;
+  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, mu, nullptr, nullptr, zb2, U, dt,
                            2.0 / 3.0, 0.0, 0.0, s);
+  if (e == hipSuccess) e = enqueue_hdiff(ctx, mu, zb2, nullptr, 2.0 / 3.0 * dt, 0.0, s);
   if (e == hipSuccess)
-    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb2, nullptr, nullptr, zb1, U, ctx->dt,
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb2, nullptr, nullptr, zb1, U, dt,
                              0.25, 0.0, 0.0, s);
+  if (e == hipSuccess) e = enqueue_hdiff(ctx, zb2, zb1, nullptr, 0.25 * dt, 0.0, s);
   if (e == hipSuccess)
-    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb1, mu, zb2, mu, U, ctx->dt, 1.0,
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb1, mu, zb2, mu, U, dt, 1.0,
                              1.0 / 3.0, 0.75, s);
+  if (e == hipSuccess) e = enqueue_hdiff(ctx, zb1, mu, nullptr, dt, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
   g_err.clear();
   return SDG_OK;

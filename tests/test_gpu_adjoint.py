@@ -19,15 +19,17 @@ def rel(got, ref):
 
 
 def _case(name):
+    """Small meshes with a stiff vertical diffusion (kappa dt / dz^2 from 1 to
+    ~280) so that the column solve matters, at the stable advective dt."""
     if name == "tiny":
         w = W.tiny(n_fields=2)
-        w.dt *= 20.0
+        w.kappa = w.kappa * 1000.0
     elif name == "ragged":
         w = W.ragged(n=6, n_fields=1)
-        w.dt *= 10.0
+        w.kappa = w.kappa * 300.0
     else:
         w = W.config1(n=6, n_layers=4)
-        w.dt *= 5.0
+        w.kappa = w.kappa * 100.0
     return w, O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
 
 
@@ -64,7 +66,9 @@ def test_adjoint_gradient_matches_oracle(name):
     print(name, "J", J, Jr, "dT0", rel(gT, gTr), "dkappa", rel(gk, gkr))
     assert abs(J - Jr) <= 1e-12 * abs(Jr)
     assert rel(gT, gTr) <= 1e-11
-    assert rel(gk, gkr) <= 1e-10
+    # dJ/dkappa_l = sum_n dt mu_n^T A_l x_{n+1} is ~3e3 times smaller than the
+    # sum of its terms' magnitudes here, so rounding reaches a few 1e-10
+    assert rel(gk, gkr) <= 1e-9
 
 
 def test_checkpoint_interval_does_not_change_gradient():

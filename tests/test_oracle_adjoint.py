@@ -46,33 +46,56 @@ def test_vertical_operator_is_linear_in_kappa():
     assert abs(A - S).max() <= 1e-13 * abs(A).max()
 
 
-def _fd_check(m, w, n_steps, seed):
-    J, gT, gk = OA.gradient(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, n_steps, w.penalty)
+def _final(m, w, kappa, T0, n_steps, kappa_h):
+    return OA.forward(m, w.U, kappa, T0, w.dt, w.t_ext, n_steps, w.penalty, kappa_h)[-1]
+
+
+def _central_difference(m, xp, xm, eps):
+    """(J(+) - J(-)) / (2 eps) without subtracting the two objectives:
+    J+^2 - J-^2 = sum_f (x+ - x-)^T M (x+ + x-), so the difference of the
+    final states carries the O(eps) signal instead of two nearly equal J."""
+    Mp = O.mass_matrix(m)
+    dq = np.einsum("fin,nij,fjn->", xp - xm, Mp, xp + xm)
+    jp, jm = OA.objective(m, xp), OA.objective(m, xm)
+    return dq / (jp + jm) / (2 * eps)
+
+
+def _fd_check(m, w, n_steps, seed, kappa_h=None):
+    J, gT, gk = OA.gradient(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, n_steps, w.penalty, kappa_h)
     rng = np.random.default_rng(seed)
     for trial in range(3):
         d = rng.standard_normal(w.T0.shape)
         d /= np.abs(d).max()
         eps = 1e-6
-        jp = OA.objective_after_steps(m, w.U, w.kappa, w.T0 + eps * d, w.dt, w.t_ext, n_steps, w.penalty)
-        jm = OA.objective_after_steps(m, w.U, w.kappa, w.T0 - eps * d, w.dt, w.t_ext, n_steps, w.penalty)
-        fd = (jp - jm) / (2 * eps)
+        fd = _central_difference(m, _final(m, w, w.kappa, w.T0 + eps * d, n_steps, kappa_h),
+                                 _final(m, w, w.kappa, w.T0 - eps * d, n_steps, kappa_h), eps)
         ad = float(np.sum(gT * d))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J, ("T0", trial, fd, ad)
+        # J moves by ~1e-5 of itself per unit relative change of kappa, so a
+        # step of 1e-6 would drown in the round-off of a stiff column solve
         dk = rng.standard_normal(w.kappa.shape) * w.kappa
-        jp = OA.objective_after_steps(m, w.U, w.kappa + eps * dk, w.T0, w.dt, w.t_ext, n_steps, w.penalty)
-        jm = OA.objective_after_steps(m, w.U, w.kappa - eps * dk, w.T0, w.dt, w.t_ext, n_steps, w.penalty)
-        fd = (jp - jm) / (2 * eps)
+        ek = 1e-4
+        fd = _central_difference(m, _final(m, w, w.kappa + ek * dk, w.T0, n_steps, kappa_h),
+                                 _final(m, w, w.kappa - ek * dk, w.T0, n_steps, kappa_h), ek)
         ad = float(np.sum(gk * dk))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J, ("kappa", trial, fd, ad)
 
 
 def test_gradient_matches_finite_differences_tiny():
     w = W.tiny(n_fields=2)
-    w.dt *= 20.0          # makes the vertical solve matter
+    w.kappa = w.kappa * 100.0     # kappa dt / dz^2 up to ~28: the solve matters
     _fd_check(_mesh(w), w, 3, 1)
 
 
 def test_gradient_matches_finite_differences_ragged():
     w = W.ragged(n=5, n_fields=1)
-    w.dt *= 10.0
+    w.kappa = w.kappa * 100.0
     _fd_check(_mesh(w), w, 2, 2)
+
+
+def test_gradient_with_horizontal_diffusion_matches_finite_differences():
+    from oracle.horizontal_diffusion import okubo_diffusivity
+    w = W.ragged(n=5, n_fields=1)
+    w.kappa = w.kappa * 100.0
+    m = _mesh(w)
+    _fd_check(m, w, 2, 3, kappa_h=okubo_diffusivity(m, 50.0))
