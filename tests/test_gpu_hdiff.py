@@ -128,6 +128,28 @@ def test_graph_replay_matches_eager():
         assert np.array_equal(g.gather(gstate), e.gather(estate)), k
 
 
+def test_config2_sampled_stage_parity():
+    """Full size (199,712 columns x 30 layers, 4 fields), Okubo's own
+    diffusivity: the three stages on 3000 sampled prisms, autotuned shape."""
+    w = W.config2()
+    m = O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
+    kh = okubo_diffusivity(m, 1.0)
+    s, U, kappa, state = upload(w, scale=1.0)
+    s.autotune(reps=2)
+    rng = np.random.default_rng([3, 9])
+    Ts_np = w.T0 + 0.05 * rng.standard_normal(w.T0.shape)
+    Ts = s.scatter(Ts_np)
+    sample = np.sort(rng.choice(m.P, 3000, replace=False))
+    for stage in range(3):
+        out = s.rk_stage(stage, state, Ts)
+        s.sync()
+        got = out[:, :, s.slots[sample]].double().cpu().numpy()
+        ref = O.rk_stage(m, w.U, stage, w.T0, Ts_np, w.dt, w.t_ext, prisms=sample, kappa_h=kh, eta=w.penalty)
+        err = rel_err(got, ref)
+        print("config2 hdiff stage", stage, err)
+        assert np.all(err <= TOL64), (stage, err)
+
+
 def test_config2_keeps_constants():
     w = W.config2()
     c = np.array([0.25, -1.5, 17.5, 35.0])
