@@ -411,7 +411,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU column "
-              f"decomposition is not part of this build", file=sys.stderr)
+              f"decomposition is designed, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

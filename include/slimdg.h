@@ -82,7 +82,7 @@ typedef enum {
   SDG_E_MESH = -2,        /* mesh description fails validation */
   SDG_E_HIP = -3,         /* HIP runtime error (message has the HIP string) */
   SDG_E_STATE = -4,       /* call made before the state it needs was set */
-  SDG_E_UNSUPPORTED = -5, /* valid request this build does not support */
+  SDG_E_UNSUPPORTED = -5, /* valid request the library does not support */
   SDG_E_NUMERIC = -6,     /* non-finite values found (check_finite) */
   SDG_E_WORKSPACE = -7    /* workspace too small or misaligned */
 } sdg_status;
