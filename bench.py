@@ -130,6 +130,18 @@ def run_gpu(w, precision, steps, warmup, torch, P_mod):
     return res
 
 
+def copy_bandwidth(torch, n_bytes=1 << 30, reps=5):
+    """Read + write GB/s of a device-to-device copy of n_bytes (torch's copy
+    kernel): the practical streaming ceiling the roofline is also quoted
+    against."""
+    src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    t = time_calls(torch, lambda: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * n_bytes / t / 1e9
+
+
 def event_time(torch, fn):
     """Seconds taken by fn() on the current stream, HIP events around it."""
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -438,6 +450,8 @@ def main():
     if args.hdiff_only:
         print(json.dumps({"hdiff_form": hdiff_form(w, 10, torch, P_mod)}), flush=True)
         return
+    copy_gbps = copy_bandwidth(torch)
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
     r64 = run_gpu(w, P_mod.SDG_FP64, args.steps, args.warmup, torch, P_mod)
     log("fp64", json.dumps(r64))
     r32 = None
@@ -489,6 +503,8 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": r64["stage_GBps"] * 1e9 / HBM_PEAK,
+            "copy_GBps": copy_gbps,
+            "frac_of_copy": r64["stage_GBps"] / copy_gbps,
             "traffic": measured_traffic(r64["tuning"]),
             "traffic_unit": "bytes per launch (mean of the 3 stage launches)",
             "algorithmic_bytes_mean_per_launch": sum(r64["stage_bytes_per_launch"]) / 3,

@@ -470,6 +470,35 @@ def test_ssp_rk3_is_third_order_taylor_on_linear_operator():
     assert np.allclose(T3.reshape(-1), ref, rtol=1e-12, atol=1e-13 * np.abs(ref).max())
 
 
+def test_whole_step_is_dense_composition():
+    """The matrix-free step equals S P(dt L) x on the tiny mesh (linear with
+    zero exterior values), with P the SSP-RK3 polynomial of the assembled L
+    and S = (M - dt A)^-1 M assembled from the column systems: the Lie
+    splitting order (three stages, then the solve) and both parts together."""
+    w = W.tiny(n_fields=1)
+    m = _mesh(w)
+    n = 6 * m.P
+    t_ext = [0.0]
+    dt = 5.0 * w.dt
+    Lmat = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros((1, 6, m.P))
+        e.reshape(-1)[j] = 1.0
+        Lmat[:, j] = O.explicit_operator(m, w.U, e, t_ext).reshape(-1)
+    A = dt * Lmat
+    P3 = np.eye(n) + A + A @ A / 2 + A @ A @ A / 6
+    # S column by column: unknowns of the state vector are (node, prism)
+    S = np.zeros((n, n))
+    for c in range(m.C):
+        K, Mc = O.column_system(m, w.kappa, dt, c)
+        ps = m.off[c] + np.arange(m.nl[c])
+        idx = (np.arange(6)[None, :] * m.P + ps[:, None]).ravel()      # column order (layer, node)
+        S[np.ix_(idx, idx)] = np.linalg.solve(K, Mc)
+    ref = S @ (P3 @ w.T0.reshape(-1))
+    got = O.step(m, w.U, w.kappa, w.T0, dt, t_ext, w.penalty).reshape(-1)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def _l2_error_vs(mesh, T, exact_fn):
     """sqrt(int (T_h - T_exact)^2) with the 12-point rule."""
     err = 0.0
