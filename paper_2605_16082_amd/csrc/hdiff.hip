@@ -18,7 +18,9 @@
 // kernel adds c1 M^-1 D to Tout (and c2 M^-1 D to Tout2), after the stage
 // kernel has written them, one thread per prism over tiles of two layers of a
 // cell (128 threads): the per-column factors are cheap to rebuild, and the
-// many independent prisms keep enough loads in flight.  kh is computed once
+// many independent prisms keep enough loads in flight.  The tile's stage
+// input is staged in LDS first, so neighbours in the same cell (most lateral
+// faces of a locality-ordered mesh) are read from there.  kh is computed once
 // per column (okubo_kernel) when the parameters are set.
 #include "internal.h"
 
@@ -59,6 +61,7 @@ template <typename R>
 struct HFace {
   bool interior;
   int nslot, depth, nA, nB;  // neighbour layer-0 slot, depth, its nodes at the edge ends A and B
+  int nlane;                 // neighbour lane when it is in the same cell, else -1
   R Le, sig, khn;            // edge length, penalty, neighbour kh
   R dn[3], dnn[3];           // n . grad(lambda) of the own and the neighbour's basis
 };
@@ -73,12 +76,24 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
   const int l = tile.layer0 + threadIdx.x / kCell;
   const int cell = tile.cell;
   const int c = cell * kCell + lane;
-  if (l >= m.nlay[c]) return;
-  const int CS = m.n_col_slots;
   const size_t S = (size_t)m.n_slots, LS = (size_t)m.n_lslots;
+  const R* Ts = static_cast<const R*>(a.Ts);
+  // the tile's stage input, [row][layer][lane]: neighbours in the same cell
+  // are read from here
+  __shared__ R sh[6 * NF][kHdiffLayers][kCell];
+  const int li = threadIdx.x / kCell;
+  const bool live = l < m.nlay[c];
+  const int64_t p = (int64_t)m.cell_base[cell] + lane + (int64_t)l * kCell;
+  if (live) {
+#pragma unroll
+    for (int r = 0; r < 6 * NF; ++r) sh[r][li][lane] = Ts[(size_t)r * S + (size_t)p];
+  }
+  __syncthreads();
+  if (!live) return;
+  const int CS = m.n_col_slots;
   const R* geo = geo_rows<R>(m);
   const R* zl = level_rows<R>(m);
-  const R* Ts = static_cast<const R*>(a.Ts);
+  const uint32_t cbase = (uint32_t)m.cell_base[cell];
   R* Out = static_cast<R*>(a.Tout);
   R* Out2 = static_cast<R*>(a.Tout2);
   const R eta = R(a.eta), c1 = R(a.c1), c2 = R(a.c2);
@@ -96,6 +111,8 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
     const int ncol = m.nbr_col[e * CS + c];
     F.interior = ncol >= 0;
     F.nslot = m.nbr_slot[e * CS + c];
+    const uint32_t nl_ = (uint32_t)F.nslot - cbase;
+    F.nlane = (F.interior && nl_ < (uint32_t)kCell) ? (int)nl_ : -1;
     const int meta = m.nbr_meta[e * CS + c];
     F.depth = F.interior ? (meta >> 2) : 0;
     const int kp = meta & 3;
@@ -117,7 +134,6 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
     F.sig = eta * R(0.5) * (kh + F.khn) / h;
   }
 
-  const int64_t p = (int64_t)m.cell_base[cell] + lane + (int64_t)l * kCell;
   const int64_t lt = (int64_t)m.cell_lbase[cell] + lane + (int64_t)l * kCell;
   {
     R dz[3];
@@ -138,7 +154,7 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
       const R* Tf = Ts + (size_t)(f * 6) * S;
       R T[6];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) T[i] = Tf[(size_t)i * S + (size_t)p];
+      for (int i = 0; i < 6; ++i) T[i] = sh[f * 6 + i][li][lane];
       R gt[2], gb[2];
 #pragma unroll
       for (int d = 0; d < 2; ++d) {
@@ -160,8 +176,13 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
         const int A = e, B = (e + 1) % 3;
         const size_t q = (size_t)F.nslot + (size_t)l * kCell;
         R Tn[6];
+        if (F.nlane >= 0) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) Tn[i] = Tf[(size_t)i * S + q];
+          for (int i = 0; i < 6; ++i) Tn[i] = sh[f * 6 + i][li][F.nlane];
+        } else {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) Tn[i] = Tf[(size_t)i * S + q];
+        }
         // normal derivatives of both sides on the top and bottom traces
         const R gnt = F.dn[0] * T[0] + F.dn[1] * T[1] + F.dn[2] * T[2];
         const R gnb = F.dn[0] * T[3] + F.dn[1] * T[4] + F.dn[2] * T[5];
