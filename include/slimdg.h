@@ -21,9 +21,15 @@
  *                            penalty vertical diffusion operator; block
  *                            tridiagonal with 6x6 blocks whose off-diagonal
  *                            blocks have the half-block sparsity of section 2.4;
- *                            always computed in FP64.
- *   step                     three rk_stage calls then one vertical solve.
+ *                            computed in FP64 (in FP32 only in SDG_FP32 contexts).
+ *   step                     three rk_stage calls then one vertical solve, or the
+ *                            two-step split-IMEX step of sections 2 and 3 (vertically
+ *                            implicit over dt/2, then explicit over dt).
  *   mass                     m_f = sum_K 1^T M_K T_K, FP64, per member and field.
+ *   column_dv_solve          the matrix-free column solves of section 2.3 (D_vu of
+ *                            the horizontal pressure gradient, D_vd of w).
+ * Optional horizontal diffusion (section 1.1, Okubo diffusivity) joins the
+ * explicit operator when sdg_params.okubo_scale > 0.
  *
  * Storage layout ("cell layout", the paper's section 2.1.1 grouping of
  * columns, here with 64 columns per cell -- one wavefront): columns keep the
