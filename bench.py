@@ -10,9 +10,14 @@ one FP64 implicit vertical-diffusion column solve.
 
 ``value`` = prism-node DOF updates per second per RK stage over whole steps:
 3 * 6 * P * F / t_step (the column solve's time is included).  The stage
-kernel's own rate and its HBM roofline fraction are reported beside it, with
-the same measurement for the FP32-state / FP64-solve form, and the FP64 CPU
-oracle timed on a bounded sample on the host.
+kernel's own rate and its HBM roofline fraction (against 8 TB/s and against
+the measured device copy rate) are reported beside it, with the same
+measurement for the FP32-state / FP64-solve form, and the FP64 CPU oracle
+timed on a bounded sample on the host.  Unless --no-extra is given the line
+also carries the precision forms after 100 steps, the split-IMEX scheme, the
+horizontal (Okubo) diffusion, the matrix-free column solves, the batched
+16-member form and the adjoint form.  --column-dv-only and --hdiff-only time
+one of those alone (for profiling).
 """
 
 from __future__ import annotations
