@@ -224,3 +224,54 @@ def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h
 
 def objective_after_steps(mesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0) -> float:
     return objective(mesh, forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta)[-1])
+
+
+def gradient_imex(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
+    """(J, dJ/dT0, dJ/dkappa) for n_steps of the split-IMEX step
+    (``split_imex.imex_step``), by reverse-mode differentiation of its two
+    steps with h = dt/2 and G = M^-1 (R + A):
+
+        x_h = (M - h A)^-1 (M x + h R x + h c),   x' = x + dt G x_h
+
+        mu      = (M - h A)^-T dt (R + A)^T M^-1 lambda'
+        lambda  = lambda' + (M + h R)^T mu
+        dJ/dkappa_l += dt lambda'^T M^-1 A_l x_h + h mu^T A_l x_h
+
+    with the same assembled operators as ``gradient`` (R includes the
+    horizontal diffusion matrix when kappa_h is given)."""
+    from .split_imex import imex_step
+    kappa = np.asarray(kappa, dtype=np.float64)
+    F = T0.shape[0]
+    h = 0.5 * dt
+    xs, xh = [np.array(T0, dtype=np.float64)], []
+    for _ in range(n_steps):
+        x1, th = imex_step(mesh, U, kappa, xs[-1], dt, t_ext, eta, return_half=True, kappa_h=kappa_h)
+        xs.append(x1)
+        xh.append(th)
+    M = mass_matrix_global(mesh).tocsc()
+    R = advection_matrix(mesh, U)
+    if kappa_h is not None:
+        from .horizontal_diffusion import horizontal_diffusion_matrix
+        R = (R + horizontal_diffusion_matrix(mesh, kappa_h, eta)).tocsr()
+    A = vertical_matrix_global(mesh, kappa, eta)
+    Kh_T = (M - h * A).T.tocsc()
+    RA_T = (R + A).T.tocsr()
+    MhR_T = (M + h * R).T.tocsr()
+    A_l = []
+    for l in range(len(kappa)):
+        e = np.zeros_like(kappa)
+        e[l] = 1.0
+        A_l.append(vertical_matrix_global(mesh, e, eta))
+    xN = _flat(xs[-1])
+    J = float(np.sqrt(np.sum(xN * (M @ xN))))
+    lam = (M @ xN) / J
+    dk = np.zeros_like(kappa)
+    for n in range(n_steps - 1, -1, -1):
+        Minv_lam = spla.spsolve(M, lam).reshape(lam.shape)
+        mu = spla.spsolve(Kh_T, dt * (RA_T @ Minv_lam)).reshape(lam.shape)
+        x_h = _flat(xh[n])
+        for l in range(len(kappa)):
+            Ax = A_l[l] @ x_h
+            dk[l] += dt * np.sum(Minv_lam * Ax) + h * np.sum(mu * Ax)
+        lam = lam + MhR_T @ mu
+    return J, _unflat(lam, F), dk

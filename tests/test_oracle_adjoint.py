@@ -99,3 +99,38 @@ def test_gradient_with_horizontal_diffusion_matches_finite_differences():
     w.kappa = w.kappa * 100.0
     m = _mesh(w)
     _fd_check(m, w, 2, 3, kappa_h=okubo_diffusivity(m, 50.0))
+
+
+def _imex_objective(m, w, kappa, T0, n_steps, kappa_h):
+    from oracle.split_imex import imex_step
+    x = T0
+    for _ in range(n_steps):
+        x = imex_step(m, w.U, kappa, x, w.dt, w.t_ext, w.penalty, kappa_h=kappa_h)
+    return x
+
+
+@pytest.mark.parametrize("with_hdiff", [False, True])
+def test_imex_gradient_matches_finite_differences(with_hdiff):
+    from oracle.horizontal_diffusion import okubo_diffusivity
+    w = W.ragged(n=5, n_fields=1)
+    w.kappa = w.kappa * 100.0
+    m = _mesh(w)
+    kh = okubo_diffusivity(m, 50.0) if with_hdiff else None
+    n_steps = 2
+    J, gT, gk = OA.gradient_imex(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, n_steps, w.penalty, kh)
+    assert abs(J - OA.objective(m, _imex_objective(m, w, w.kappa, w.T0, n_steps, kh))) <= 1e-13 * J
+    rng = np.random.default_rng(7)
+    for trial in range(3):
+        d = rng.standard_normal(w.T0.shape)
+        d /= np.abs(d).max()
+        eps = 1e-6
+        fd = _central_difference(m, _imex_objective(m, w, w.kappa, w.T0 + eps * d, n_steps, kh),
+                                 _imex_objective(m, w, w.kappa, w.T0 - eps * d, n_steps, kh), eps)
+        ad = float(np.sum(gT * d))
+        assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J, ("T0", trial, fd, ad)
+        dk = rng.standard_normal(w.kappa.shape) * w.kappa
+        ek = 1e-4
+        fd = _central_difference(m, _imex_objective(m, w, w.kappa + ek * dk, w.T0, n_steps, kh),
+                                 _imex_objective(m, w, w.kappa - ek * dk, w.T0, n_steps, kh), ek)
+        ad = float(np.sum(gk * dk))
+        assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J, ("kappa", trial, fd, ad)
