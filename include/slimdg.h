@@ -78,7 +78,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 5
+#define SDG_ABI_VERSION 6
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -329,6 +329,23 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
  * an unknown kind, n_comp out of range or a NULL pointer gives SDG_E_ARG.
  * Enqueued on the context stream; does not synchronise. */
 sdg_status sdg_column_dv_solve(sdg_ctx* ctx, int kind, int n_comp, const void* dev_F, void* dev_x);
+
+/* Reverse of one split-IMEX sdg_step (FP64 contexts with
+ * SDG_SCHEME_SPLIT_IMEX only, SDG_E_UNSUPPORTED otherwise): not in the paper;
+ * the exact transpose of the two-step scheme of sections 2 and 3 in the same
+ * variable Z = M^-1 lambda as sdg_step_adjoint, with h = dt/2 and
+ * L~ = M^-1 (R_lin + D)^T:
+ *   w      = 2 (Z^{n+1} + h L~ Z^{n+1})
+ *   mu'    = (M - h A^T)^-1 M w                      (transposed column solve)
+ *   Z^n    = mu' + h L~ mu' + Z^{n+1} - w
+ *   dkappa[l] += h mu'^T (dA/dkappa_l) x_h           (if dev_dkappa != NULL)
+ * with x_h the vertically implicit half step from dev_x_prev, the state
+ * BEFORE the forward step being reversed (rebuilt here when dkappa is asked
+ * for).  dev_z_next, dev_z_out, dev_x_prev: [n_fields][6][n_slots] doubles;
+ * dev_z_out must not alias dev_z_next or dev_x_prev; dev_dkappa: [max_layers]
+ * doubles, accumulated.  Uses the workspace stage buffers. */
+sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_prev,
+                                 double* dev_dkappa);
 
 /* Wait for the context's stream and report any asynchronous HIP error. */
 sdg_status sdg_sync(sdg_ctx* ctx);

@@ -6,7 +6,9 @@ runs the library's adjoint step in reverse: the forward pass keeps only every
 ``checkpoint_every``-th state; each segment is recomputed from its checkpoint
 (storing the post-solve states it needs) and then reversed step by step.  The
 adjoint state is carried as Z = M^-1 lambda; the returned gradients are
-dJ/dT0 = M Z_0 and dJ/dkappa (per layer).
+dJ/dT0 = M Z_0 and dJ/dkappa (per layer).  Both time schemes are reversed:
+SSP-RK3 + Lie with the state after each step, split-IMEX with the state
+before it.
 
 ``MNorm.apply(x, model)`` is J = sqrt(sum_f x_f^T M x_f), whose gradient is
 M x / J.  Both use only library kernels on the device.
@@ -17,6 +19,8 @@ from __future__ import annotations
 import math
 
 import torch
+
+from .slimdg import SDG_SCHEME_SPLIT_IMEX, SDG_SCHEME_SSPRK3_LIE
 
 
 class TracerSteps(torch.autograd.Function):
@@ -53,12 +57,18 @@ class TracerSteps(torch.autograd.Function):
             k = min(ctx.every, ctx.n_steps - start)
             st = ctx.ckpts[i].clone()
             s.set_fields(st)
-            xs = []
+            xs = [st.clone()]                    # states before step 0 .. after step k-1
             for _ in range(k):
                 s.step(1)
                 xs.append(st.clone())
             for j in range(k - 1, -1, -1):
-                s.step_adjoint(z, z, xs[j], dk)
+                if getattr(s, "time_scheme", SDG_SCHEME_SSPRK3_LIE) == SDG_SCHEME_SPLIT_IMEX:
+                    # the split-IMEX reverse step takes the state before the step
+                    zn = torch.empty_like(z)
+                    s.step_adjoint_imex(z, zn, xs[j], dk)
+                    z = zn
+                else:
+                    s.step_adjoint(z, z, xs[j + 1], dk)
         grad_T0 = s.apply_mass(z)
         return grad_T0, dk, None, None, None
 

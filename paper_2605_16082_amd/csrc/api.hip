@@ -938,6 +938,63 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   return SDG_OK;
 }
 
+sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_prev,
+                                 double* dev_dkappa) {
+  sdg_status st = check_explicit(ctx, "sdg_step_adjoint_imex");
+  if (st != SDG_OK) return st;
+  if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint_imex needs an FP64 context");
+  if (ctx->scheme != SDG_SCHEME_SPLIT_IMEX)
+    return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint_imex reverses the split-IMEX step only");
+  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint_imex needs sdg_set_diffusivity");
+  if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint_imex: NULL buffer");
+  if (dev_z_out == dev_z_next || dev_z_out == dev_x_prev)
+    return fail(SDG_E_ARG, "sdg_step_adjoint_imex: z_out must not alias z_next or x_prev");
+  if (dev_dkappa && !dev_x_prev) return fail(SDG_E_ARG, "sdg_step_adjoint_imex: dkappa needs x_prev");
+  void* A = ctx->stage_a;
+  void* B = ctx->stage_b;
+  if (dev_z_out == A || dev_z_out == B || dev_z_next == A || dev_z_next == B || dev_x_prev == A || dev_x_prev == B)
+    return fail(SDG_E_ARG, "sdg_step_adjoint_imex: buffers must not be the workspace stage buffers");
+  DeviceGuard g(ctx->device);
+  const Plan& P = ctx->plan;
+  hipStream_t s = ctx->stream;
+  const double h = 0.5 * ctx->dt;
+  const int choice = ctx->tile_choice < kThreadTileChoices ? ctx->tile_choice : 1;
+  const int tl = kTileLayerOptions[choice];
+  const WgTile* tiles = ctx->tiles[choice];
+  const int nt = P.n_tiles[choice];
+  const bool wz = ctx->w_zero;
+  const double* U = static_cast<const double*>(ctx->U);
+  const double* Z1 = static_cast<const double*>(dev_z_next);
+  double* out = static_cast<double*>(dev_z_out);
+  double* mu = static_cast<double*>(A);
+  double* w = static_cast<double*>(B);
+  hipError_t e = hipSuccess;
+  if (dev_dkappa) {
+    // x_h of the step being reversed, kept in z_out until the last stage:
+    // the half step from x_prev, then its column solve in place
+    StageArgs s1 = stage_args(ctx, nullptr, dev_x_prev, dev_z_out, 0.0, 1.0, h);
+    e = launch_stage(s1, false, wz, false, false, s);
+    if (e == hipSuccess) e = hdiff_after_stage(ctx, s1, h, 0.0, s);
+    if (e != hipSuccess) return hip_fail(e, "split-IMEX adjoint half step launch");
+    if ((st = enqueue_solve(ctx, dev_z_out, dev_z_out, h, s)) != SDG_OK) return st;
+  }
+  // w = 2 (Z1 + h L~ Z1)
+  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, Z1, nullptr, nullptr, w, U, h, 2.0, 0.0,
+                           0.0, s);
+  if (e == hipSuccess) e = enqueue_hdiff(ctx, Z1, w, nullptr, 2.0 * h, 0.0, s);
+  // mu' = (M - h A^T)^-1 M w;  dJ/dkappa_l += h mu'^T A_l x_h
+  if (e == hipSuccess) e = launch_tsolve(ctx->dm, P.F, w, mu, ctx->kappa, ctx->scratch, h, ctx->eta, s);
+  if (e == hipSuccess && dev_dkappa)
+    e = launch_kappa_gradient(ctx->dm, P.F, mu, out, ctx->kpart, ctx->eta, h, dev_dkappa, s);
+  // Z0 = mu' + h L~ mu' + Z1 - w
+  if (e == hipSuccess)
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, mu, Z1, w, out, U, h, 1.0, 1.0, -1.0, s);
+  if (e == hipSuccess) e = enqueue_hdiff(ctx, mu, out, nullptr, h, 0.0, s);
+  if (e != hipSuccess) return hip_fail(e, "split-IMEX adjoint launch");
+  g_err.clear();
+  return SDG_OK;
+}
+
 sdg_status sdg_column_dv_solve(sdg_ctx* ctx, int kind, int n_comp, const void* dev_F, void* dev_x) {
   if (!ctx || !dev_F || !dev_x) return fail(SDG_E_ARG, "sdg_column_dv_solve: NULL argument");
   if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_column_dv_solve needs an uploaded mesh");

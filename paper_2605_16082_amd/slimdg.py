@@ -30,7 +30,7 @@ EXPORTED = (
     "sdg_set_fields", "sdg_rhs_3d", "sdg_rk_stage", "sdg_vertical_implicit_solve", "sdg_step",
     "sdg_mass", "sdg_sync", "sdg_get_tuning", "sdg_set_tuning", "sdg_autotune",
     "sdg_graph_capture_step", "sdg_graph_launch", "sdg_apply_mass", "sdg_m_dot", "sdg_step_adjoint",
-    "sdg_column_dv_solve",
+    "sdg_column_dv_solve", "sdg_step_adjoint_imex",
 )
 
 
@@ -127,6 +127,7 @@ def load_library(path: str | None = None):
         "sdg_m_dot": ([vp, vp, vp, vp], i32),
         "sdg_step_adjoint": ([vp, vp, vp, vp, vp], i32),
         "sdg_column_dv_solve": ([vp, i32, i32, vp, vp], i32),
+        "sdg_step_adjoint_imex": ([vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -264,6 +265,7 @@ class SlimDG:
         p = Params(float(dt), float(penalty_eta), text.ctypes.data, int(bool(w_is_zero)), int(bool(check_finite)),
                    int(time_scheme), float(okubo_scale))
         _check(self.lib.sdg_set_params(self.ctx, ctypes.byref(p)))
+        self.time_scheme = int(time_scheme)
 
     def set_velocity(self, U):
         self._check_nodal(U, 3)
@@ -352,6 +354,18 @@ class SlimDG:
         out = np.zeros(self.mesh.n_members * self.n_fields, dtype=np.float64)
         _check(self.lib.sdg_m_dot(self.ctx, _ptr(X), _ptr(Y), out.ctypes.data))
         return out.reshape(self.mesh.n_members, self.n_fields)
+
+    def step_adjoint_imex(self, z_next, z_out, x_prev=None, dkappa=None):
+        """Reverse of one split-IMEX step; x_prev is the state before that step."""
+        self._check_nodal(z_next, self.n_fields)
+        self._check_nodal(z_out, self.n_fields)
+        if x_prev is not None:
+            self._check_nodal(x_prev, self.n_fields)
+        if dkappa is not None and (dkappa.dtype != self.torch.float64 or dkappa.numel() < int(self.layout.max_layers)):
+            raise ValueError("dkappa must be a float64 device tensor with >= max_layers entries")
+        _check(self.lib.sdg_step_adjoint_imex(self.ctx, _ptr(z_next), _ptr(z_out),
+                                              None if x_prev is None else _ptr(x_prev),
+                                              None if dkappa is None else _ptr(dkappa)))
 
     def step_adjoint(self, z_next, z_out, x_next=None, dkappa=None):
         self._check_nodal(z_next, self.n_fields)

@@ -166,3 +166,52 @@ def test_config5_gradient_finite_differences():
         worst = max(worst, abs(fd - ad) / abs(ad))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J, ("kappa", trial, fd, ad)
     print("config5 J", J, "worst relative FD mismatch", worst)
+
+
+def _gpu_gradient_imex(w, n_steps, every, okubo_scale=0.0):
+    import torch
+    s, U, kappa, state = P.from_workload(w, time_scheme=P.SDG_SCHEME_SPLIT_IMEX, okubo_scale=okubo_scale)
+    T0 = s.scatter(w.T0).requires_grad_(True)
+    kap = torch.as_tensor(w.kappa, dtype=torch.float64, device=s.device).requires_grad_(True)
+    xN = P.TracerSteps.apply(T0, kap, s, n_steps, every)
+    J = P.MNorm.apply(xN, s)
+    J.backward()
+    return float(J), s.gather(T0.grad), kap.grad.detach().cpu().numpy(), s
+
+
+@pytest.mark.parametrize("name,okubo", [("tiny", 0.0), ("ragged", 0.0), ("config1", 0.0), ("ragged", 50.0)])
+def test_imex_adjoint_matches_oracle(name, okubo):
+    from oracle.horizontal_diffusion import okubo_diffusivity
+    w, m = _case(name)
+    n_steps = 3
+    J, gT, gk, s = _gpu_gradient_imex(w, n_steps, 2, okubo)
+    kh = okubo_diffusivity(m, okubo) if okubo > 0 else None
+    Jr, gTr, gkr = OA.gradient_imex(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, n_steps, w.penalty, kh)
+    print(name, okubo, "J", J, Jr, "dT0", rel(gT, gTr), "dkappa", rel(gk, gkr))
+    assert abs(J - Jr) <= 1e-12 * abs(Jr)
+    assert rel(gT, gTr) <= 1e-11
+    assert rel(gk, gkr) <= 1e-9          # cancelling sum of terms, as for the Lie step
+
+
+def test_imex_checkpoint_interval_does_not_change_gradient():
+    w, m = _case("ragged")
+    ref = None
+    for every in (1, 3, 7):
+        J, gT, gk, s = _gpu_gradient_imex(w, 7, every)
+        if ref is None:
+            ref = (gT, gk)
+        else:
+            assert np.array_equal(gT, ref[0]) and np.array_equal(gk, ref[1]), every
+
+
+def test_imex_adjoint_argument_errors():
+    w, m = _case("tiny")
+    s, U, kappa, state = P.from_workload(w, time_scheme=P.SDG_SCHEME_SPLIT_IMEX)
+    z = s.new_state()
+    with pytest.raises(P.SlimDGError) as e:
+        s.step_adjoint_imex(z, z, state)           # z_out aliases z_next
+    assert e.value.status == -1
+    lie, _, _, lstate = P.from_workload(w)
+    with pytest.raises(P.SlimDGError) as e:
+        lie.step_adjoint_imex(lie.new_state(), lie.new_state(), lstate)
+    assert e.value.status == -5
