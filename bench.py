@@ -365,6 +365,22 @@ def adjoint_form(torch, P_mod, W, n_steps=200, every=20):
            "ms_per_adjoint_step": t_adj * 1e3, "ms_per_forward_step": t_step * 1e3}
     del s, U, kappa, x, T0, kap, z
     torch.cuda.empty_cache()
+    # the same for the split-IMEX scheme
+    s, U, kappa, x = P_mod.from_workload(w, time_scheme=P_mod.SDG_SCHEME_SPLIT_IMEX)
+    s.autotune(reps=2)
+    s.step(2)
+    s.set_fields(x.copy_(s.scatter(w.T0)))
+    t_fwd = event_time(torch, lambda: s.step(n_steps))
+    T0 = s.scatter(w.T0).requires_grad_(True)
+    kap = torch.as_tensor(w.kappa, dtype=torch.float64, device=s.device).requires_grad_(True)
+    t_grad = event_time(torch, grad)
+    z, zo = s.new_state(), s.new_state()
+    t_adj = time_calls(torch, lambda: s.step_adjoint_imex(z, zo, x, kap.grad), reps)
+    t_step = time_calls(torch, lambda: s.step(1), reps)
+    out["split_imex"] = {"t_forward_s": t_fwd, "t_gradient_s": t_grad, "gradient_over_forward": t_grad / t_fwd,
+                         "ms_per_adjoint_step": t_adj * 1e3, "ms_per_forward_step": t_step * 1e3}
+    del s, U, kappa, x, T0, kap, z, zo
+    torch.cuda.empty_cache()
     return out
 
 
