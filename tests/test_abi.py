@@ -94,6 +94,8 @@ def test_rejects_malformed_meshes():
     tri = w.tri.copy()
     tri[1, 2] = len(w.vxy)
     assert _status(lambda: P.Mesh(w.vxy, tri, w.nbr, w.nlayers, w.zlev, 1).layout()) == -2
+    # no triangles at all
+    assert _status(lambda: P.Mesh(w.vxy, w.tri[:0], w.nbr[:0], w.nlayers[:0], w.zlev[:0], 1).layout()) == -2
     # unsupported field count
     assert _status(lambda: P.Mesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev, 5).layout()) == -5
     assert _status(lambda: P.Mesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev, 0).layout()) == -5
