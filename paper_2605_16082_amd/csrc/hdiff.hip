@@ -20,8 +20,10 @@
 // cell (128 threads): the per-column factors are cheap to rebuild, and the
 // many independent prisms keep enough loads in flight.  The tile's stage
 // input is staged in LDS first, so neighbours in the same cell (most lateral
-// faces of a locality-ordered mesh) are read from there.  kh is computed once
-// per column (okubo_kernel) when the parameters are set.
+// faces of a locality-ordered mesh) are read from there.  A field's current
+// output values are loaded before its arithmetic rather than at the update, so
+// that their latency overlaps it.  kh is computed once per column
+// (okubo_kernel) when the parameters are set.
 #include "internal.h"
 
 namespace sdg {
@@ -152,6 +154,14 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const R* Tf = Ts + (size_t)(f * 6) * S;
+      // the field's current output values, loaded before its arithmetic
+      R o[6], o2[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const size_t oi = (size_t)(f * 6 + i) * S + (size_t)p;
+        o[i] = Out[oi];
+        o2[i] = OUT2 ? Out2[oi] : R(0);
+      }
       R T[6];
 #pragma unroll
       for (int i = 0; i < 6; ++i) T[i] = sh[f * 6 + i][li][lane];
@@ -234,9 +244,9 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
       L[5] = sc * (k02 * hb[0] + k12 * hb[1] + k22 * hb[2]);
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
-        const size_t o = (size_t)(f * 6 + i) * S + (size_t)p;
-        Out[o] += c1 * L[i];
-        if (OUT2) Out2[o] += c2 * L[i];
+        const size_t oi = (size_t)(f * 6 + i) * S + (size_t)p;
+        Out[oi] = o[i] + c1 * L[i];
+        if (OUT2) Out2[oi] = o2[i] + c2 * L[i];
       }
     }
   }
