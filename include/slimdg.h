@@ -186,7 +186,9 @@ sdg_status sdg_destroy(sdg_ctx* ctx);
  * (>= workspace_bytes, 256-byte aligned), then compute the per-column
  * geometry on the device (the extruded triangle mesh of section 1; J_h of
  * the 2D mass matrix of section 2.3).  Synchronises the stream.  Any
- * previously set velocity / diffusivity / fields are forgotten. */
+ * previously set params / velocity / diffusivity / fields are forgotten
+ * (params hold per-field exterior values and, with okubo_scale > 0, a
+ * per-column diffusivity of the old mesh): set them again. */
 sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_workspace,
                            size_t workspace_bytes);
 

@@ -49,7 +49,7 @@ struct Plan {
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_stage_a, o_stage_b, o_scratch,
-      o_colmass, o_msum, o_flag, o_kpart, o_kh, total;
+      o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, total;
   size_t state_bytes, velocity_bytes;
 };
 
@@ -193,6 +193,7 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_flag = take(sizeof(int32_t) * 64);
   P.o_kpart = take(sizeof(double) * (size_t)P.max_layers * (size_t)P.n_cells);
   P.o_kh = take(sizeof(double) * (size_t)P.CS);
+  P.o_hface = take(sizeof(double) * 15 * (size_t)P.CS);
   P.total = o;
   return SDG_OK;
 }
@@ -237,6 +238,7 @@ struct sdg_ctx {
   int32_t* flag = nullptr;
   double* kpart = nullptr;
   double* kh = nullptr;     // per-column horizontal diffusivity (workspace)
+  double* hface = nullptr;  // per-face neighbour table of the horizontal diffusion (workspace)
   void* stage_a = nullptr;
   void* stage_b = nullptr;
   double* scratch = nullptr;
@@ -336,6 +338,8 @@ sdg_status sdg_destroy(sdg_ctx* ctx) {
 sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_workspace, size_t ws_bytes) {
   if (!ctx) return fail(SDG_E_ARG, "context is NULL");
   ctx->have_mesh = false;
+  ctx->have_params = false;   // t_ext and the horizontal diffusivity belong to the mesh
+  ctx->kh_scale = 0.0;
   ctx->graph_valid = false;
   ctx->U = nullptr;
   ctx->kappa = nullptr;
@@ -448,6 +452,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   ctx->flag = reinterpret_cast<int32_t*>(ws + Q.o_flag);
   ctx->kpart = reinterpret_cast<double*>(ws + Q.o_kpart);
   ctx->kh = reinterpret_cast<double*>(ws + Q.o_kh);
+  ctx->hface = reinterpret_cast<double*>(ws + Q.o_hface);
   ctx->stage_a = ws + Q.o_stage_a;
   ctx->stage_b = ws + Q.o_stage_b;
   ctx->scratch = reinterpret_cast<double*>(ws + Q.o_scratch);
@@ -476,7 +481,7 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
     // Okubo: K = 0.0103 l^1.15 cm^2/s with l in cm = 0.0103 100^1.15 1e-4 l^1.15 m^2/s, l in m
     DeviceGuard g(ctx->device);
     const double coef = p->okubo_scale * 0.0103 * std::pow(100.0, 1.15) * 1.0e-4;
-    hipError_t e = launch_okubo(ctx->dm, coef, ctx->kh, ctx->stream);
+    hipError_t e = launch_hdiff_setup(ctx->dm, coef, eta, ctx->kh, ctx->hface, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "horizontal diffusivity launch");
   }
   for (int f = 0; f < ctx->plan.F; ++f) ctx->t_ext[f] = text[f];
@@ -568,7 +573,7 @@ hipError_t enqueue_hdiff(sdg_ctx* ctx, const void* Ts, void* Tout, void* Tout2, 
   h.c1 = c1;
   h.c2 = c2;
   h.kh = ctx->kh;
-  h.eta = ctx->eta;
+  h.hface = ctx->hface;
   return launch_hdiff(h, ctx->plan.fp32, strm);
 }
 

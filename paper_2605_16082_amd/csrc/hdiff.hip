@@ -22,8 +22,10 @@
 // input is staged in LDS first, so neighbours in the same cell (most lateral
 // faces of a locality-ordered mesh) are read from there.  A field's current
 // output values are loaded before its arithmetic rather than at the update, so
-// that their latency overlaps it.  kh is computed once per column
-// (okubo_kernel) when the parameters are set.
+// that their latency overlaps it.  When the parameters are set, kh is computed
+// once per column (okubo_kernel) and, per column and lateral face, what the
+// face terms need of the neighbour (hface_kernel), so that the kernel's loads
+// of per-column data do not wait on the neighbour's index.
 #include "internal.h"
 
 namespace sdg {
@@ -56,6 +58,38 @@ __global__ __launch_bounds__(256) void okubo_kernel(DevMesh m, double coef, doub
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= m.n_col_slots) return;
   kh[c] = m.nlay[c] > 0 ? coef * pow(m.geo[G_JH * m.n_col_slots + c], 0.575) : 0.0;
+}
+
+// Rows of the per-face table, [face][row][column slot]: the neighbour's kh,
+// the penalty sigma, and n . grad(lambda') of the neighbour's three vertices
+// (n the face's outward normal); zero on faces without a neighbour.
+constexpr int kHfRows = 5;
+
+__global__ __launch_bounds__(256) void hface_kernel(DevMesh m, const double* kh, double eta, double* hf) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int CS = m.n_col_slots;
+  if (c >= CS) return;
+  const double* geo = m.geo;
+  double gl[3][2], Jh;
+  lambda_grads<double>(geo, CS, c, gl, Jh);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int ncol = m.nlay[c] > 0 ? m.nbr_col[e * CS + c] : -1;
+    double v[kHfRows] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ncol >= 0) {
+      const double nx = geo[(G_NX + e) * CS + c], ny = geo[(G_NY + e) * CS + c];
+      const double Le = geo[(G_LE + e) * CS + c];
+      double gn[3][2], Jn;
+      lambda_grads<double>(geo, CS, ncol, gn, Jn);
+      v[0] = kh[ncol];
+      const double h = (Jh < Jn ? Jh : Jn) / Le;
+      v[1] = eta * 0.5 * (kh[c] + v[0]) / h;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) v[2 + j] = nx * gn[j][0] + ny * gn[j][1];
+    }
+#pragma unroll
+    for (int r = 0; r < kHfRows; ++r) hf[(size_t)(e * kHfRows + r) * CS + c] = v[r];
+  }
 }
 
 // Field-independent data of one lateral face of a column.
@@ -98,7 +132,7 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
   const uint32_t cbase = (uint32_t)m.cell_base[cell];
   R* Out = static_cast<R*>(a.Tout);
   R* Out2 = static_cast<R*>(a.Tout2);
-  const R eta = R(a.eta), c1 = R(a.c1), c2 = R(a.c2);
+  const R c1 = R(a.c1), c2 = R(a.c2);
 
   R gl[3][2], Jh;
   lambda_grads<R>(geo, CS, c, gl, Jh);
@@ -110,9 +144,8 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
     HFace<R>& F = fc[e];
     const R nx = geo[(G_NX + e) * CS + c], ny = geo[(G_NY + e) * CS + c];
     F.Le = geo[(G_LE + e) * CS + c];
-    const int ncol = m.nbr_col[e * CS + c];
-    F.interior = ncol >= 0;
     F.nslot = m.nbr_slot[e * CS + c];
+    F.interior = F.nslot >= 0;
     const uint32_t nl_ = (uint32_t)F.nslot - cbase;
     F.nlane = (F.interior && nl_ < (uint32_t)kCell) ? (int)nl_ : -1;
     const int meta = m.nbr_meta[e * CS + c];
@@ -122,18 +155,11 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
     F.nB = kp;
 #pragma unroll
     for (int j = 0; j < 3; ++j) F.dn[j] = nx * gl[j][0] + ny * gl[j][1];
-    R gn[3][2], Jn = Jh;
-    if (F.interior) {
-      lambda_grads<R>(geo, CS, ncol, gn, Jn);
-    } else {
+    const double* hfe = a.hface + (size_t)(e * kHfRows) * CS + c;
+    F.khn = R(hfe[0]);
+    F.sig = R(hfe[(size_t)CS]);
 #pragma unroll
-      for (int j = 0; j < 3; ++j) gn[j][0] = gn[j][1] = R(0);
-    }
-    F.khn = F.interior ? R(a.kh[ncol]) : R(0);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) F.dnn[j] = nx * gn[j][0] + ny * gn[j][1];
-    const R h = (Jh < Jn ? Jh : Jn) / F.Le;
-    F.sig = eta * R(0.5) * (kh + F.khn) / h;
+    for (int j = 0; j < 3; ++j) F.dnn[j] = R(hfe[(size_t)(2 + j) * CS]);
   }
 
   const int64_t lt = (int64_t)m.cell_lbase[cell] + lane + (int64_t)l * kCell;
@@ -267,10 +293,14 @@ hipError_t launch_nf(const HdiffArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_okubo(const DevMesh& m, double coef, double* kh, hipStream_t s) {
+hipError_t launch_hdiff_setup(const DevMesh& m, double coef, double eta, double* kh, double* hface,
+                              hipStream_t s) {
   const int n = m.n_col_slots;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(okubo_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, coef, kh);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hface_kernel, dim3((n + 255) / 256), dim3(256), 0, s, m, kh, eta, hface);
   return hipGetLastError();
 }
 

@@ -103,13 +103,16 @@ struct HdiffArgs {
   void* Tout2;           // optional
   double c1, c2;
   const double* kh;      // [n_col_slots] horizontal diffusivity per column
-  double eta;
+  const double* hface;   // [3 faces][5][n_col_slots]: neighbour kh, penalty, n . grad of its basis
 };
 
 // Kernel launchers (defined next to their kernels).
 hipError_t launch_hdiff(const HdiffArgs& a, bool fp32, hipStream_t s);
 // kh[c] = coef * sqrt(J_h)^1.15 for every live column.
-hipError_t launch_okubo(const DevMesh& m, double coef, double* kh, hipStream_t s);
+// kh per column (coef sqrt(J_h)^1.15) and the per-face neighbour table of the
+// horizontal diffusion (penalty factor eta)
+hipError_t launch_hdiff_setup(const DevMesh& m, double coef, double eta, double* kh, double* hface,
+                              hipStream_t s);
 hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStream_t s);
 hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,

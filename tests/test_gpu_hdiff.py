@@ -205,3 +205,26 @@ def test_argument_errors():
         with pytest.raises(P.SlimDGError) as e:
             s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, okubo_scale=bad)
         assert e.value.status == -1
+
+
+def test_mesh_upload_forgets_params():
+    """A mesh upload drops the parameters, whose exterior values and per-column
+    diffusivity belong to the old mesh: the operator refuses to run until they
+    are set again, and then matches the oracle."""
+    import ctypes
+    from paper_2605_16082_amd.slimdg import _check, _ptr
+
+    w, m = case("config1")
+    s, U, kappa, state = upload(w)
+    _check(s.lib.sdg_mesh_upload(s.ctx, ctypes.byref(s.mesh.desc), _ptr(s.workspace),
+                                 int(s.layout.workspace_bytes)))
+    s.set_velocity(U)
+    with pytest.raises(P.SlimDGError) as e:
+        s.rhs_3d(state)
+    assert e.value.status == -4
+    s.set_params(w.dt, w.t_ext, w.penalty, w.w_is_zero, okubo_scale=SCALE)
+    L = s.rhs_3d(state)
+    s.sync()
+    kh = okubo_diffusivity(m, SCALE)
+    err = rel_err(s.gather(L), O.explicit_operator(m, w.U, w.T0, w.t_ext, kappa_h=kh, eta=w.penalty))
+    assert np.all(err <= TOL64), err
