@@ -622,7 +622,13 @@ struct WalkLayout {
   static constexpr int kU = pad(6 * NF);
   static constexpr int kZ = kU + pad(kNU);
   static constexpr int kBase = kZ + pad(3);
-  static constexpr bool kTnLds = READ_TN && 2 * (kBase + pad(6 * NF)) * kCell * (int)sizeof(R) <= kWalkLdsBytes;
+  // Tn joins the layer copy only where two slots with it stay within one
+  // wavefront's share of the CU's LDS: 40 KB in FP64 (one wavefront per
+  // SIMD), 20 KB in FP32 (two).  In FP32 with 4 fields it would not, and
+  // holding it there cut the residency to five wavefronts per CU (stages 1
+  // and 2: 0.94 against 0.72 ms with Tn read from global memory).
+  static constexpr bool kTnLds =
+      READ_TN && 2 * (kBase + pad(6 * NF)) * kCell * (int)sizeof(R) <= kWalkLdsBytes / (sizeof(R) == 8 ? 1 : 2);
   static constexpr int kTn = kBase;
   static constexpr int kRows = kBase + (kTnLds ? pad(6 * NF) : 0);
   static constexpr int kSlot = kRows * kCell;         // values of type R per slot
