@@ -954,6 +954,12 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
         vu[n] = ldb(U + (size_t)(1 * 6 + 3 + n) * S, pup);
         wu[n] = WZ ? R(0) : ldb(U + (size_t)(2 * 6 + 3 + n) * S, pup);
       }
+      // the layer above's bottom values, requested with its velocity before the wait
+      R Tu[NF][3];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int n = 0; n < 3; ++n) Tu[f][n] = ldb(Ts + (size_t)(f * 6 + 3 + n) * S, pup);
       wait_vm();
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
@@ -965,13 +971,10 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
       hface_factors<R, WZ>(cg, cs.zt, l0 > 0, uu, vu, wu, true, ul, vl, wl, top);
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        R Tu[3], Tl[3];
+        R Tl[3];
 #pragma unroll
-        for (int n = 0; n < 3; ++n) {
-          Tu[n] = ldb(Ts + (size_t)(f * 6 + 3 + n) * S, pup);
-          Tl[n] = slot0[(Ly::kTs + f * 6 + n) * kCell + lane];
-        }
-        hface_field<R>(top, R(a.t_ext[f]), Tu, Tl, cs.gtop[f]);
+        for (int n = 0; n < 3; ++n) Tl[n] = slot0[(Ly::kTs + f * 6 + n) * kCell + lane];
+        hface_field<R>(top, R(a.t_ext[f]), Tu[f], Tl, cs.gtop[f]);
       }
     }
     // layers in pairs so that each half names its slots statically
