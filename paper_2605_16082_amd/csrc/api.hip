@@ -359,9 +359,19 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   std::vector<double> xy(6 * (size_t)CS, 0.0), zl(3 * (size_t)P.n_lslots, 0.0);
   std::vector<WgTile> tiles[kTileChoices];
   for (int t = 0; t < kTileChoices; ++t) {
+    const int T = kTileLayerOptions[t];
     tiles[t].reserve(P.n_tiles[t]);
     for (int k = 0; k < P.n_cells; ++k)
-      for (int l0 = 0; l0 < P.cell_depth[k]; l0 += kTileLayerOptions[t]) tiles[t].push_back({k, l0});
+      for (int l0 = 0; l0 < P.cell_depth[k]; l0 += T) tiles[t].push_back({k, l0});
+    // Full tiles first, shorter ones (a cell's last segment) after them, each
+    // group in cell order.  A persistent grid strides through the table with
+    // a stride that is a multiple of 8; in cell order every workgroup would
+    // get the same segment of each cell it visits, and those that get the
+    // short last segments would idle while the others finish.  The shorter
+    // tiles also make up the tail of a one-tile-per-workgroup launch.
+    std::stable_sort(tiles[t].begin(), tiles[t].end(), [&](const WgTile& x, const WgTile& y) {
+      return std::min(T, P.cell_depth[x.cell] - x.layer0) > std::min(T, P.cell_depth[y.cell] - y.layer0);
+    });
   }
   for (int m = 0; m < P.n_members; ++m)
     for (int c = P.member_off[m]; c < P.member_off[m + 1]; ++c) colmem[c] = m;
