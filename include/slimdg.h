@@ -252,7 +252,7 @@ sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
  * throughput depending on the column block shape; here the library measures
  * it).  Results do not depend on it (bitwise).
  * tile_layers: 1, 2 or 4 = layers per workgroup of 64 columns, one thread per
- *   prism (default 2); 8, 16 or 32 = one wavefront walks that many layers of
+ *   prism (default 2); 8, 12, 16 or 32 = one wavefront walks that many layers of
  *   a cell, prefetching the next layer into LDS while computing the current;
  * xcd_remap: 1 = give each XCD one contiguous range of tiles (default);
  * persistent: 1 = launch only as many workgroups as the device holds at once,

@@ -420,8 +420,9 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
       {P.o_tiles[3], tiles[3].data(), sizeof(WgTile) * tiles[3].size()},
       {P.o_tiles[4], tiles[4].data(), sizeof(WgTile) * tiles[4].size()},
       {P.o_tiles[5], tiles[5].data(), sizeof(WgTile) * tiles[5].size()},
+      {P.o_tiles[6], tiles[6].data(), sizeof(WgTile) * tiles[6].size()},
   };
-  static_assert(kTileChoices == 6, "one copy per tile table");
+  static_assert(kTileChoices == 7, "one copy per tile table");
   for (const Cp& cp : cps) {
     if (cp.bytes == 0) continue;
     hipError_t e = hipMemcpyAsync(ws + cp.off, cp.src, cp.bytes, hipMemcpyHostToDevice, s);
@@ -751,7 +752,7 @@ sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* t) {
   int choice = -1;
   for (int i = 0; i < kTileChoices; ++i)
     if (kTileLayerOptions[i] == t->tile_layers) choice = i;
-  if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2, 4, 8, 16 or 32 (got %d)", t->tile_layers);
+  if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2, 4, 8, 12, 16 or 32 (got %d)", t->tile_layers);
   if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(SDG_E_ARG, "xcd_remap must be 0 or 1");
   if (t->persistent != 0 && t->persistent != 1) return fail(SDG_E_ARG, "persistent must be 0 or 1");
   ctx->tile_choice = choice;

@@ -56,8 +56,8 @@ struct WgTile {
   int32_t cell;
   int32_t layer0;
 };
-constexpr int kTileChoices = 6;
-constexpr int kTileLayerOptions[kTileChoices] = {1, 2, 4, 8, 16, 32};
+constexpr int kTileChoices = 7;
+constexpr int kTileLayerOptions[kTileChoices] = {1, 2, 4, 8, 12, 16, 32};
 constexpr int kWalkMinLayers = 8;
 constexpr int kThreadTileChoices = 3;           // choices 0..2 run one thread per prism
 

@@ -36,7 +36,8 @@ def ensemble():
 # column-walk kernel
 SHAPES = [(4, 1, 0), (1, 0, 1), (8, 1, 0), (2, 1, 1), (16, 0, 1), (1, 1, 0), (32, 1, 1), (4, 0, 1),
           (2, 0, 0), (8, 0, 1), (1, 0, 0), (16, 1, 0), (4, 1, 1), (32, 0, 0), (2, 1, 0), (8, 1, 1),
-          (1, 1, 1), (16, 0, 0), (4, 0, 0), (32, 1, 0), (2, 0, 1), (8, 0, 0), (16, 1, 1), (32, 0, 1)]
+          (1, 1, 1), (16, 0, 0), (4, 0, 0), (32, 1, 0), (2, 0, 1), (8, 0, 0), (16, 1, 1), (32, 0, 1),
+          (12, 1, 0), (12, 0, 1), (12, 1, 1), (12, 0, 0)]
 
 
 @pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32])
@@ -67,7 +68,7 @@ def test_persistent_grid_walks_many_tiles():
     s, U, kappa, state = P.from_workload(w)
     rng = np.random.default_rng(8)
     Ts = s.scatter(w.T0 + 0.1 * rng.standard_normal(w.T0.shape))
-    for tl in (1, 2, 4, 8, 16, 32):
+    for tl in (1, 2, 4, 8, 12, 16, 32):
         outs = []
         for x, pers in ((1, 0), (1, 1), (0, 1)):
             s.set_tuning(tl, x, pers)
@@ -95,7 +96,7 @@ def test_autotune_keeps_results():
     a = P.from_workload(w)
     b = P.from_workload(w)
     choice = a[0].autotune(reps=3)
-    assert choice[0] in (1, 2, 4, 8, 16, 32) and choice[1] in (0, 1) and choice[2] in (0, 1)
+    assert choice[0] in (1, 2, 4, 8, 12, 16, 32) and choice[1] in (0, 1) and choice[2] in (0, 1)
     a[0].step(2)
     b[0].step(2)
     a[0].sync()
