@@ -260,12 +260,17 @@ __device__ __forceinline__ void lat_nb(const StageArgs& a, const LatMeta<R>& M, 
   }
 }
 
-// Upwind weights at the 3 x 2 face points, max(q, 0) and min(q, 0) with
-// q = u_n dS, u_n the normal component of the average of the two velocity
-// traces (a wall carries no flux).
+// Upwind weights at the 3 x 2 face points from q = u_n dS, u_n the normal
+// component of the average of the two velocity traces (a wall carries no
+// flux): the flux is q times the inner trace where q > 0, else the outer one.
 template <typename R>
 struct LatF {
-  R up[3][2], um[3][2];
+  // FP64 keeps the signed weight q alone, and picks the upwind trace by its
+  // sign (the one wavefront per SIMD runs short of registers: 1.5-2% faster);
+  // FP32 keeps max(q, 0) and min(q, 0) (2% slower the other way).
+  static constexpr bool kSigned = sizeof(R) == 8;
+  R up[3][2];                    // q (FP64) or max(q, 0) (FP32)
+  R um[kSigned ? 1 : 3][2];      // min(q, 0) (FP32 only)
   uint32_t no[4];
   bool interior;
   bool lds;
@@ -298,8 +303,12 @@ __device__ __forceinline__ void lat_factors(const LatMeta<R>& M, const LatNb<R>&
     for (int k = 0; k < 2; ++k) {
       const R tk = R(kZt[k]), bk = R(kZb[k]);
       const R q = (s1 * (tk * un[0] + bk * un[2]) + s * (tk * un[1] + bk * un[3])) * dS;
-      F.up[j][k] = upos(q);
-      F.um[j][k] = uneg(q);
+      if constexpr (LatF<R>::kSigned) {
+        F.up[j][k] = q;
+      } else {
+        F.up[j][k] = upos(q);
+        F.um[j][k] = uneg(q);
+      }
     }
   }
 }
@@ -329,7 +338,11 @@ __device__ __forceinline__ void lat_field(int e, const LatF<R>& F, const R T[6],
       const R tk = R(kZt[k]), bk = R(kZb[k]);
       const R ti = s1 * (tk * T[A] + bk * T[A + 3]) + s * (tk * T[B] + bk * T[B + 3]);
       const R tq = s1 * (tk * to[0] + bk * to[2]) + s * (tk * to[1] + bk * to[3]);
-      const R fl = F.up[j][k] * ti + F.um[j][k] * tq;
+      R fl;
+      if constexpr (LatF<R>::kSigned)
+        fl = F.up[j][k] * (F.up[j][k] > R(0) ? ti : tq);
+      else
+        fl = F.up[j][k] * ti + F.um[j][k] * tq;
       res[A] -= s1 * tk * fl;
       res[B] -= s * tk * fl;
       res[A + 3] -= s1 * bk * fl;
