@@ -304,7 +304,7 @@ def batched_form(torch, P_mod, W, steps, warmup):
     the FP64 path on the same members, with the per-field error between them
     after warmup + steps steps."""
     t0 = time.perf_counter()
-    w = W.config4()
+    w = W.zlevel_ensemble()
     log(f"batched workload built in {time.perf_counter() - t0:.1f} s: {w.n_cols} columns, "
         f"{w.n_prisms} prisms, layers {int(w.nlayers.min())}-{int(w.nlayers.max())}")
     P, F = w.n_prisms, w.n_fields
@@ -341,7 +341,7 @@ def adjoint_form(torch, P_mod, W, n_steps=200, every=20):
     """Gradient of J = sqrt(x_N^T M x_N) with respect to the initial field and
     the per-layer diffusivity through the hand-written adjoint, with a
     checkpoint every `every` steps, against the plain forward run."""
-    w = W.config5()
+    w = W.adjoint_blob()
     s, U, kappa, x = P_mod.from_workload(w)
     s.autotune(reps=2)
     s.step(2)
@@ -462,7 +462,7 @@ def main():
             torch.cuda.synchronize()
         del src, dst
     t0 = time.perf_counter()
-    w = W.config2(n=args.n, n_layers=args.layers)
+    w = W.four_field_ocean(n=args.n, n_layers=args.layers)
     log(f"workload built in {time.perf_counter() - t0:.1f} s: {w.n_cols} columns, {w.n_prisms} prisms, "
         f"{w.n_fields} fields")
     if args.column_dv_only:

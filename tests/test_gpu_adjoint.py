@@ -28,7 +28,7 @@ def _case(name):
         w = W.ragged(n=6, n_fields=1)
         w.kappa = w.kappa * 300.0
     else:
-        w = W.config1(n=6, n_layers=4)
+        w = W.rotating_blob(n=6, n_layers=4)
         w.kappa = w.kappa * 100.0
     return w, O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
 
@@ -45,7 +45,7 @@ def _gpu_gradient(w, n_steps, every):
 
 
 def test_mass_apply_and_m_dot():
-    w, m = _case("config1")
+    w, m = _case("rotating_blob")
     s, U, kappa, state = P.from_workload(w)
     Mp = O.mass_matrix(m)
     ref = np.einsum("nij,fjn->fin", Mp, w.T0)
@@ -57,7 +57,7 @@ def test_mass_apply_and_m_dot():
     assert abs(md - float(np.einsum("fin,fin->", ref, w.T0))) <= 1e-12 * abs(md)
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "config1"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "rotating_blob"])
 def test_adjoint_gradient_matches_oracle(name):
     w, m = _case(name)
     n_steps = 3
@@ -86,7 +86,7 @@ def test_adjoint_matches_finite_differences_on_gpu():
     """Directional derivatives against central differences (eps = 1e-6) of
     the GPU forward objective, on a 7,200-column x 12-layer mesh."""
     import torch
-    w = W.config1(n=60, n_layers=12)
+    w = W.rotating_blob(n=60, n_layers=12)
     w.kappa = np.geomspace(1e-2, 1e-5, 12)
     w.dt *= 2.0
     n_steps, every = 30, 10
@@ -117,7 +117,7 @@ def test_adjoint_matches_finite_differences_on_gpu():
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J
 
 
-def test_config5_gradient_finite_differences():
+def test_adjoint_blob_gradient_finite_differences():
     """The differentiation configuration in full: 49,928 triangles x 20
     layers, 200 steps, a checkpoint every 20; 20 seeded directions for the
     initial field and 20 for the per-layer diffusivity, central differences
@@ -129,7 +129,7 @@ def test_config5_gradient_finite_differences():
     J+^2 - J-^2 = (x+ - x-)^T M (x+ + x-), subtracted slot by slot before
     the sum, divided by J+ + J-."""
     import torch
-    w = W.config5()
+    w = W.adjoint_blob()
     n_steps, every = w.n_steps, 20
     J, gT, gk, s = _gpu_gradient(w, n_steps, every)
     st = s.new_state()
@@ -165,7 +165,7 @@ def test_config5_gradient_finite_differences():
         ad = float(np.sum(gk * dk))
         worst = max(worst, abs(fd - ad) / abs(ad))
         assert abs(fd - ad) <= 1e-6 * abs(ad) + 1e-10 * J, ("kappa", trial, fd, ad)
-    print("config5 J", J, "worst relative FD mismatch", worst)
+    print("adjoint_blob J", J, "worst relative FD mismatch", worst)
 
 
 def _gpu_gradient_imex(w, n_steps, every, okubo_scale=0.0):
@@ -179,7 +179,7 @@ def _gpu_gradient_imex(w, n_steps, every, okubo_scale=0.0):
     return float(J), s.gather(T0.grad), kap.grad.detach().cpu().numpy(), s
 
 
-@pytest.mark.parametrize("name,okubo", [("tiny", 0.0), ("ragged", 0.0), ("config1", 0.0), ("ragged", 50.0)])
+@pytest.mark.parametrize("name,okubo", [("tiny", 0.0), ("ragged", 0.0), ("rotating_blob", 0.0), ("ragged", 50.0)])
 def test_imex_adjoint_matches_oracle(name, okubo):
     from oracle.horizontal_diffusion import okubo_diffusivity
     w, m = _case(name)

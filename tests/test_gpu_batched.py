@@ -64,7 +64,7 @@ def test_persistent_grid_walks_many_tiles():
     """A mesh with several times more tiles than the chip holds at once, so
     every persistent workgroup walks several tiles: bitwise the same stage
     output as one workgroup per tile, for every tile height and remap."""
-    w = W.config1(n=100, n_layers=20, seed=4)
+    w = W.rotating_blob(n=100, n_layers=20, seed=4)
     s, U, kappa, state = P.from_workload(w)
     rng = np.random.default_rng(8)
     Ts = s.scatter(w.T0 + 0.1 * rng.standard_normal(w.T0.shape))
@@ -160,11 +160,11 @@ def test_ensemble_step_and_member_mass_parity():
     assert np.allclose(mass0, ref_mass, rtol=1e-13, atol=0), (mass0, ref_mass)
 
 
-def test_batched_config_sampled_parity():
+def test_zlevel_ensemble_sampled_parity():
     """16 members, 1.1M ragged z-level columns (5-60 layers), FP32 state with
     the FP64 solve, checked on sampled prisms and columns against the FP64
     oracle fed the same (FP32-representable) inputs."""
-    w = W.config4()
+    w = W.zlevel_ensemble()
     # the GPU holds FP32 copies of the inputs: feed the oracle the same values
     w.U = w.U.astype(np.float32).astype(np.float64)
     w.T0 = w.T0.astype(np.float32).astype(np.float64)
@@ -178,7 +178,7 @@ def test_batched_config_sampled_parity():
     got = out[:, :, s.slots[sample]].double().cpu().numpy()
     ref = O.rk_stage(m, w.U, 1, w.T0, w.T0, w.dt, w.t_ext, prisms=sample)
     err = rel_err(got, ref)
-    print("config4 stage 1", err)
+    print("zlevel_ensemble stage 1", err)
     assert np.all(err <= 5e-5), err
     cols = np.sort(rng.choice(m.C, 100, replace=False))
     out = s.vertical_implicit_solve(state)
@@ -186,5 +186,5 @@ def test_batched_config_sampled_parity():
     ref_full = O.implicit_solve(m, w.kappa, w.dt, w.T0, w.penalty, columns=cols)
     pr = np.concatenate([m.off[c] + np.arange(m.nl[c]) for c in cols])
     err = rel_err(out[:, :, s.slots[pr]].double().cpu().numpy(), ref_full[:, :, pr])
-    print("config4 solve", err)
+    print("zlevel_ensemble solve", err)
     assert np.all(err <= 5e-5), err

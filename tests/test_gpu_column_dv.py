@@ -33,8 +33,8 @@ def _workload(name):
         return W.ragged(seed=1)
     if name == "deep_ragged":     # 162 columns, 1..37 layers
         return W.ragged(seed=3, n=9, n_min=1, n_max=37, depth_max=190.0)
-    if name == "config1":         # 1800 columns x 10 layers
-        return W.config1()
+    if name == "rotating_blob":         # 1800 columns x 10 layers
+        return W.rotating_blob()
     if name == "single":          # one prism
         w = W.tiny(n=1, n_layers=1)
         return W.Workload("single", w.vxy, w.tri[:1], np.full((1, 3), -1, np.int32), w.nlayers[:1],
@@ -56,7 +56,7 @@ def _reference(kind, w, F, precision):
     return CD.dv_solve(kind, w.vxy, w.tri, w.nlayers, Fin)
 
 
-@pytest.mark.parametrize("name", ["single", "ragged", "deep_ragged", "config1"])
+@pytest.mark.parametrize("name", ["single", "ragged", "deep_ragged", "rotating_blob"])
 @pytest.mark.parametrize("kind", ["vu", "vd"])
 def test_column_dv_parity(name, kind):
     w = _workload(name)
@@ -118,12 +118,12 @@ def test_column_dv_argument_errors():
 
 @pytest.fixture(scope="module")
 def big():
-    return W.config2()
+    return W.four_field_ocean()
 
 
 @pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32_STATE_FP64_SOLVE])
 @pytest.mark.parametrize("kind,n_comp", [("vu", 2), ("vd", 1)])
-def test_column_dv_config2_sampled(big, kind, n_comp, precision):
+def test_column_dv_four_field_ocean_sampled(big, kind, n_comp, precision):
     """Full size (199,712 columns x 30 layers), checked on 300 sampled columns."""
     w = big
     s = _session(w, precision)
@@ -140,5 +140,5 @@ def test_column_dv_config2_sampled(big, kind, n_comp, precision):
         Fs = Fs.astype(np.float32).astype(np.float64)
     ref = CD.dv_solve(kind, w.vxy, w.tri[cols], w.nlayers[cols], Fs)
     err = rel_err(got, ref)
-    print("config2", kind, n_comp, precision, err)
+    print("four_field_ocean", kind, n_comp, precision, err)
     assert np.all(err <= TOL[precision]), err

@@ -29,7 +29,7 @@ def upload(w, precision=P.SDG_FP64, scheme=P.SDG_SCHEME_SSPRK3_LIE, scale=SCALE)
     return P.from_workload(w, precision, time_scheme=scheme, okubo_scale=scale)
 
 
-@pytest.mark.parametrize("name", ["tiny", "single", "config1", "ragged", "deep_ragged"])
+@pytest.mark.parametrize("name", ["tiny", "single", "rotating_blob", "ragged", "deep_ragged"])
 def test_pure_diffusion_operator(name):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -44,7 +44,7 @@ def test_pure_diffusion_operator(name):
     assert np.all(err <= TOL64), err
 
 
-@pytest.mark.parametrize("name", ["config1", "ragged", "wnonzero"])
+@pytest.mark.parametrize("name", ["rotating_blob", "ragged", "wnonzero"])
 def test_rhs_and_stages_with_advection(name):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -65,9 +65,9 @@ def test_rhs_and_stages_with_advection(name):
         assert np.all(err <= TOL64), (stage, err)
 
 
-@pytest.mark.parametrize("scheme,name,n_steps", [(P.SDG_SCHEME_SSPRK3_LIE, "config1", 3),
+@pytest.mark.parametrize("scheme,name,n_steps", [(P.SDG_SCHEME_SSPRK3_LIE, "rotating_blob", 3),
                                                  (P.SDG_SCHEME_SSPRK3_LIE, "deep_ragged", 2),
-                                                 (P.SDG_SCHEME_SPLIT_IMEX, "config1", 3),
+                                                 (P.SDG_SCHEME_SPLIT_IMEX, "rotating_blob", 3),
                                                  (P.SDG_SCHEME_SPLIT_IMEX, "ragged", 2)])
 def test_steps_with_horizontal_diffusion(scheme, name, n_steps):
     w, m = case(name)
@@ -88,7 +88,7 @@ def test_steps_with_horizontal_diffusion(scheme, name, n_steps):
 
 @pytest.mark.parametrize("precision", [P.SDG_FP32_STATE_FP64_SOLVE, P.SDG_FP32])
 def test_float_forms(precision):
-    w, m = case("config1")
+    w, m = case("rotating_blob")
     s, U, kappa, state = upload(w, precision)
     kh = okubo_diffusivity(m, SCALE)
     s.step(3)
@@ -128,10 +128,10 @@ def test_graph_replay_matches_eager():
         assert np.array_equal(g.gather(gstate), e.gather(estate)), k
 
 
-def test_config2_sampled_stage_parity():
+def test_four_field_ocean_sampled_stage_parity():
     """Full size (199,712 columns x 30 layers, 4 fields), Okubo's own
     diffusivity: the three stages on 3000 sampled prisms, autotuned shape."""
-    w = W.config2()
+    w = W.four_field_ocean()
     m = O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
     kh = okubo_diffusivity(m, 1.0)
     s, U, kappa, state = upload(w, scale=1.0)
@@ -146,12 +146,12 @@ def test_config2_sampled_stage_parity():
         got = out[:, :, s.slots[sample]].double().cpu().numpy()
         ref = O.rk_stage(m, w.U, stage, w.T0, Ts_np, w.dt, w.t_ext, prisms=sample, kappa_h=kh, eta=w.penalty)
         err = rel_err(got, ref)
-        print("config2 hdiff stage", stage, err)
+        print("four_field_ocean hdiff stage", stage, err)
         assert np.all(err <= TOL64), (stage, err)
 
 
-def test_config2_keeps_constants():
-    w = W.config2()
+def test_four_field_ocean_keeps_constants():
+    w = W.four_field_ocean()
     c = np.array([0.25, -1.5, 17.5, 35.0])
     w.T0 = np.broadcast_to(c[:, None, None], w.T0.shape).copy()
     w.t_ext = c.copy()
@@ -160,7 +160,7 @@ def test_config2_keeps_constants():
     s.sync()
     got = state[:, :, s.slots].double()
     dev = (got - s.torch.as_tensor(c, device=got.device)[:, None, None]).abs().amax(dim=(1, 2)).cpu().numpy()
-    print("config2 constants", dev)
+    print("four_field_ocean constants", dev)
     assert np.all(dev <= 1e-12 * np.abs(c).max()), dev
 
 
@@ -214,7 +214,7 @@ def test_mesh_upload_forgets_params():
     import ctypes
     from paper_2605_16082_amd.slimdg import _check, _ptr
 
-    w, m = case("config1")
+    w, m = case("rotating_blob")
     s, U, kappa, state = upload(w)
     _check(s.lib.sdg_mesh_upload(s.ctx, ctypes.byref(s.mesh.desc), _ptr(s.workspace),
                                  int(s.layout.workspace_bytes)))

@@ -26,7 +26,7 @@ def upload(w, precision=P.SDG_FP64):
     return P.from_workload(w, precision, time_scheme=IMEX)
 
 
-@pytest.mark.parametrize("name,n_steps", [("tiny", 2), ("single", 2), ("config1", 4), ("ragged", 3),
+@pytest.mark.parametrize("name,n_steps", [("tiny", 2), ("single", 2), ("rotating_blob", 4), ("ragged", 3),
                                           ("deep_ragged", 2), ("wnonzero", 2)])
 def test_imex_step_parity(name, n_steps):
     w, m = case(name)
@@ -61,7 +61,7 @@ def test_imex_stiff_diffusion_parity():
 
 @pytest.mark.parametrize("precision", [P.SDG_FP32_STATE_FP64_SOLVE, P.SDG_FP32])
 def test_imex_float_forms(precision):
-    w, m = case("config1")
+    w, m = case("rotating_blob")
     s, U, kappa, state = upload(w, precision)
     s.step(4)
     s.sync()
@@ -88,7 +88,7 @@ def test_imex_launch_shapes_bitwise(shape):
 
 
 def test_imex_graph_replay_matches_eager():
-    w, m = case("config1")
+    w, m = case("rotating_blob")
     g, _, _, gstate = upload(w)
     e, _, _, estate = upload(w)
     g.graph_capture_step()
@@ -100,8 +100,8 @@ def test_imex_graph_replay_matches_eager():
         assert np.array_equal(g.gather(gstate), e.gather(estate)), k
 
 
-def test_imex_config2_keeps_constants():
-    w = W.config2()
+def test_imex_four_field_ocean_keeps_constants():
+    w = W.four_field_ocean()
     c = np.array([0.25, -1.5, 17.5, 35.0])
     w.T0 = np.broadcast_to(c[:, None, None], w.T0.shape).copy()
     w.t_ext = c.copy()
@@ -111,7 +111,7 @@ def test_imex_config2_keeps_constants():
     s.sync()
     got = state[:, :, s.slots].double()
     dev = (got - s.torch.as_tensor(c, device=got.device)[:, None, None]).abs().amax(dim=(1, 2)).cpu().numpy()
-    print("config2 constants", dev)
+    print("four_field_ocean constants", dev)
     assert np.all(dev <= 1e-12 * np.abs(c).max()), dev
 
 

@@ -43,12 +43,12 @@ def case(name):
     if name not in _CASES:
         if name == "tiny":
             w = W.tiny(n_fields=2)
-        elif name == "config1":
-            w = W.config1()
+        elif name == "rotating_blob":
+            w = W.rotating_blob()
         elif name == "ragged":
             w = W.ragged()
         elif name == "wnonzero":
-            w = W.config1(n=7, n_layers=4)
+            w = W.rotating_blob(n=7, n_layers=4)
             w.U = _random_velocity(w)
             w.w_is_zero = False
         elif name == "single":
@@ -71,7 +71,7 @@ def upload(w, precision=P.SDG_FP64):
     return s, U, kappa, state
 
 
-@pytest.mark.parametrize("name", ["tiny", "single", "config1", "ragged", "wnonzero", "deep_ragged"])
+@pytest.mark.parametrize("name", ["tiny", "single", "rotating_blob", "ragged", "wnonzero", "deep_ragged"])
 def test_rhs_3d_parity(name):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -84,7 +84,7 @@ def test_rhs_3d_parity(name):
     assert np.all(err <= TOL64), err
 
 
-@pytest.mark.parametrize("name", ["config1", "ragged", "wnonzero"])
+@pytest.mark.parametrize("name", ["rotating_blob", "ragged", "wnonzero"])
 def test_rk_stage_parity(name):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -101,7 +101,7 @@ def test_rk_stage_parity(name):
         assert np.all(err <= TOL64), (stage, err)
 
 
-@pytest.mark.parametrize("name", ["tiny", "single", "config1", "ragged", "deep_ragged"])
+@pytest.mark.parametrize("name", ["tiny", "single", "rotating_blob", "ragged", "deep_ragged"])
 def test_vertical_solve_parity(name):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -123,7 +123,7 @@ def test_vertical_solve_parity(name):
     assert np.all(rel_err(s.gather(tmp), ref) <= TOL64)
 
 
-@pytest.mark.parametrize("name,n_steps", [("config1", 10), ("ragged", 4), ("wnonzero", 3)])
+@pytest.mark.parametrize("name,n_steps", [("rotating_blob", 10), ("ragged", 4), ("wnonzero", 3)])
 def test_step_parity(name, n_steps):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -138,7 +138,7 @@ def test_step_parity(name, n_steps):
     assert np.all(err <= TOL64), err
 
 
-@pytest.mark.parametrize("name", ["config1", "ragged", "deep_ragged"])
+@pytest.mark.parametrize("name", ["rotating_blob", "ragged", "deep_ragged"])
 def test_mass_parity(name):
     w, m = case(name)
     s, U, kappa, state = upload(w)
@@ -148,7 +148,7 @@ def test_mass_parity(name):
 
 
 def test_step_is_deterministic():
-    w, m = case("config1")
+    w, m = case("rotating_blob")
     a = upload(w)
     b = upload(w)
     a[0].step(3)
@@ -171,7 +171,7 @@ def test_check_finite_reports_nan():
     assert e.value.status == -6
 
 
-@pytest.mark.parametrize("name", ["config1", "ragged"])
+@pytest.mark.parametrize("name", ["rotating_blob", "ragged"])
 def test_fp32_state_form(name):
     """FP32 state/fluxes with the FP64 column solve: bounded error vs the
     FP64 oracle after a few steps, and mass sums in FP64."""
@@ -196,11 +196,11 @@ _REF10 = {}
 
 
 @pytest.mark.parametrize("precision", [P.SDG_FP32_STATE_FP64_SOLVE, P.SDG_FP32])
-def test_fp32_forms_config1_run(precision):
-    """Config 1 in full (10 steps) in the FP32-state/FP64-solve form and in
+def test_fp32_forms_rotating_blob_run(precision):
+    """The rotating blob (1,800 triangles x 10 layers) in full (10 steps) in the FP32-state/FP64-solve form and in
     FP32 everywhere, against the FP64 oracle: per-field max-norm error within
     2e-5 of the field's maximum, total mass within 1e-6 relative."""
-    w, m = case("config1")
+    w, m = case("rotating_blob")
     if "ref" not in _REF10:
         ref = w.T0
         for _ in range(w.n_steps):
@@ -217,7 +217,7 @@ def test_fp32_forms_config1_run(precision):
     assert np.all(dm <= 1e-6), dm
 
 
-@pytest.mark.parametrize("name", ["config1", "deep_ragged"])
+@pytest.mark.parametrize("name", ["rotating_blob", "deep_ragged"])
 def test_fp32_everywhere_solve(name):
     """The FP32 column solve against the FP64 oracle's dense solve."""
     w, m = case(name)
@@ -233,15 +233,15 @@ def test_fp32_everywhere_solve(name):
 
 @pytest.fixture(scope="module")
 def big():
-    w = W.config2()
+    w = W.four_field_ocean()
     m = O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
     return w, m
 
 
 @pytest.mark.parametrize("precision,shape", [(P.SDG_FP64, None), (P.SDG_FP32_STATE_FP64_SOLVE, None),
                                              (P.SDG_FP64, (16, 1, 0)), (P.SDG_FP32_STATE_FP64_SOLVE, (8, 1, 1))])
-def test_config2_sampled_parity(big, precision, shape):
-    """Full-size config (199,712 columns x 30 layers, 4 fields), checked on
+def test_four_field_ocean_sampled_parity(big, precision, shape):
+    """Full-size workload (199,712 columns x 30 layers, 4 fields), checked on
     sampled prisms/columns: in the launch shape the autotuner picks for the
     benchmark, and in column-walk shapes."""
     w, m = big
@@ -259,7 +259,7 @@ def test_config2_sampled_parity(big, precision, shape):
         got = out[:, :, slots].double().cpu().numpy()
         ref = O.rk_stage(m, w.U, stage, w.T0, Ts_np, w.dt, w.t_ext, prisms=sample)
         err = rel_err(got, ref)
-        print("config2 stage", stage, err)
+        print("four_field_ocean stage", stage, err)
         assert np.all(err <= tol), (stage, err)
     cols = np.sort(rng.choice(m.C, 200, replace=False))
     out = s.vertical_implicit_solve(Ts)
@@ -268,5 +268,5 @@ def test_config2_sampled_parity(big, precision, shape):
     pr = (m.off[cols][:, None] + np.arange(30)[None, :]).ravel()
     got = out[:, :, s.slots[pr]].double().cpu().numpy()
     err = rel_err(got, ref_full[:, :, pr])
-    print("config2 solve", err)
+    print("four_field_ocean solve", err)
     assert np.all(err <= (TOL64 if precision == P.SDG_FP64 else 5e-5)), err

@@ -20,7 +20,7 @@ def test_assembled_advection_matches_matrix_free(name):
     if name == "ragged":
         w = W.ragged(n=6, n_fields=2)
     else:
-        w = W.config1(n=5, n_layers=3)
+        w = W.rotating_blob(n=5, n_layers=3)
         rng = np.random.default_rng([5, 7])
         w.U = w.U + 0.05 * rng.standard_normal(w.U.shape)
         w.U[2] = 1e-3 * rng.standard_normal(w.U[2].shape)

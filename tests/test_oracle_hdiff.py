@@ -55,7 +55,7 @@ def test_okubo_units():
 
 @pytest.mark.parametrize("mesh", ["ragged", "sigma"])
 def test_constants_and_conservation(mesh):
-    w = W.ragged(seed=2, n=5, n_fields=1) if mesh == "ragged" else W.config1(n=5, n_layers=3)
+    w = W.ragged(seed=2, n=5, n_fields=1) if mesh == "ragged" else W.rotating_blob(n=5, n_layers=3)
     m = _mesh(w)
     kh = okubo_diffusivity(m, 50.0)
     D1 = horizontal_diffusion_term(m, kh, np.full((1, 6, m.P), 3.0))
@@ -68,7 +68,7 @@ def test_constants_and_conservation(mesh):
 
 @pytest.mark.parametrize("mesh", ["ragged", "sigma"])
 def test_symmetric_negative_semidefinite(mesh):
-    w = W.ragged(seed=5, n=3, n_fields=1, n_max=4) if mesh == "ragged" else W.config1(n=3, n_layers=2)
+    w = W.ragged(seed=5, n=3, n_fields=1, n_max=4) if mesh == "ragged" else W.rotating_blob(n=3, n_layers=2)
     m = _mesh(w)
     kh = okubo_diffusivity(m, 10.0) * np.linspace(0.5, 2.0, m.C)       # varying kh per column
     D = _matrix(m, kh)
@@ -99,7 +99,7 @@ def test_linear_field_flat_layers():
 
 
 def test_linear_field_sloped_layers_closed_form():
-    w = W.config1(n=6, n_layers=3)
+    w = W.rotating_blob(n=6, n_layers=3)
     m = _mesh(w)
     kh = np.full(m.C, 2.0)
     a, b = 0.4, 0.9

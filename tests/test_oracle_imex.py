@@ -42,7 +42,7 @@ def test_pure_diffusion_is_crank_nicolson():
 
 
 def test_pure_advection_is_explicit_midpoint():
-    w = W.config1(n=5, n_layers=3)
+    w = W.rotating_blob(n=5, n_layers=3)
     m = _mesh(w)
     rng = np.random.default_rng(3)
     T0 = w.T0 + 0.1 * rng.standard_normal(w.T0.shape)
@@ -54,7 +54,7 @@ def test_pure_advection_is_explicit_midpoint():
 
 
 def test_mass_budget_identity():
-    w = W.config1(n=6, n_layers=4)
+    w = W.rotating_blob(n=6, n_layers=4)
     m = _mesh(w)
     kappa = np.geomspace(1e-1, 1e-3, 4)
     T1, Th = imex_step(m, w.U, kappa, w.T0, w.dt, w.t_ext, return_half=True)

@@ -295,7 +295,7 @@ def test_interior_faces_match_point_location():
 # ---------------------------------------------------------------------------
 
 def test_constant_preservation_solid_body_rotation():
-    w = W.config1(n=6, n_layers=3)
+    w = W.rotating_blob(n=6, n_layers=3)
     m = _mesh(w)
     c = 3.7
     T = np.full((1, 6, m.P), c)
@@ -305,7 +305,7 @@ def test_constant_preservation_solid_body_rotation():
 
 
 def test_budget_identity_one_step():
-    w = W.config1(n=6, n_layers=4)
+    w = W.rotating_blob(n=6, n_layers=4)
     m = _mesh(w)
     Tn1, (T1, T2, _) = O.step(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, return_stages=True)
     dm = O.mass(m, Tn1) - O.mass(m, w.T0)
@@ -317,7 +317,7 @@ def test_budget_identity_one_step():
 def _closed_flow(n=8, n_layers=3, seed=0, U0=200.0):
     """psi_h = P1 interpolant of sin(pi x/L) sin(pi y/L); U = U0 (d psi_h/dy,
     -d psi_h/dx, 0) per triangle; sigma layers over h = 20 + 10 psi_h."""
-    w = W.config1(seed=seed, n=n, n_layers=n_layers)
+    w = W.rotating_blob(seed=seed, n=n, n_layers=n_layers)
     L = W.prism_mesh.DOMAIN_L
     psi = np.sin(np.pi * w.vxy[:, 0] / L) * np.sin(np.pi * w.vxy[:, 1] / L)
     p = w.vxy[w.tri]

@@ -15,10 +15,10 @@ from .prism_mesh import (  # noqa: F401
     zlevel_levels,
     solid_body_velocity,
     cfl_dt,
-    config1,
-    config2,
-    config4,
-    config5,
+    rotating_blob,
+    four_field_ocean,
+    zlevel_ensemble,
+    adjoint_blob,
     small_ensemble,
     tiny,
     ragged,

@@ -242,7 +242,7 @@ def _blob(x, y, cx=7000.0, cy=5000.0, sigma=1000.0):
     return np.exp(-((x - cx) ** 2 + (y - cy) ** 2) / (2.0 * sigma ** 2))
 
 
-def config1(seed: int = 0, n: int = 30, n_layers: int = 10) -> Workload:
+def rotating_blob(seed: int = 0, n: int = 30, n_layers: int = 10) -> Workload:
     """Plain method, FP64: 31x31-vertex split squares (1800 triangles) with
     20% jitter, 10 sigma layers over h = 20 + 10 sin sin, solid-body rotation
     (0.5 m/s max, w = 0), Gaussian blob (sigma 1 km, centre (7 km, 5 km),
@@ -252,22 +252,22 @@ def config1(seed: int = 0, n: int = 30, n_layers: int = 10) -> Workload:
     x, y, _ = prism_node_xyz(vxy, tri, nl, zlev)
     U = solid_body_velocity(x, y)
     T0 = _blob(x, y)[None]
-    return Workload("config1", vxy, tri, nbr, nl, zlev, U, T0,
+    return Workload("rotating_blob", vxy, tri, nbr, nl, zlev, U, T0,
                     kappa=np.full(n_layers, 1e-3), dt=cfl_dt(vxy, tri, U),
                     t_ext=np.zeros(1), n_steps=10)
 
 
-def config5(seed: int = 0, n: int = 158, n_layers: int = 20) -> Workload:
-    """Differentiation form: the config1 tracer problem on 158 x 158 split
+def adjoint_blob(seed: int = 0, n: int = 158, n_layers: int = 20) -> Workload:
+    """Differentiation form: the rotating-blob tracer problem on 158 x 158 split
     squares (49,928 triangles) x 20 sigma layers (998,560 prisms), FP64, 200
     steps with a checkpoint every 20."""
-    w = config1(seed=seed, n=n, n_layers=n_layers)
-    w.name = "config5"
+    w = rotating_blob(seed=seed, n=n, n_layers=n_layers)
+    w.name = "adjoint_blob"
     w.n_steps = 200
     return w
 
 
-def config2(seed: int = 0, n: int = 316, n_layers: int = 30) -> Workload:
+def four_field_ocean(seed: int = 0, n: int = 316, n_layers: int = 30) -> Workload:
     """FP64 vs FP32 at scale: n=316 split squares (199,712 triangles), 30 sigma
     layers (5,991,360 prisms), 4 advected scalars: u, v (the rotation's
     components), temperature 25 + 15 z/h + U(+-0.1), salinity 35 + U(+-0.5);
@@ -284,7 +284,7 @@ def config2(seed: int = 0, n: int = 316, n_layers: int = 30) -> Workload:
     T0 = np.stack([U[0], U[1], temp, salt])
     lvl = np.arange(n_layers, dtype=np.float64)
     kappa = 10.0 ** (-2.0 - 3.0 * lvl / max(n_layers - 1, 1))
-    return Workload("config2", vxy, tri, nbr, nl, zlev, U, T0, kappa=kappa,
+    return Workload("four_field_ocean", vxy, tri, nbr, nl, zlev, U, T0, kappa=kappa,
                     dt=cfl_dt(vxy, tri, U), t_ext=np.array([0.0, 0.0, 17.5, 35.0]),
                     n_steps=100)
 
@@ -350,14 +350,14 @@ def _concat_members(parts):
             np.concatenate(zl), np.array(moff, dtype=np.int32))
 
 
-def config4(seed: int = 0, n_members: int = 16, n_lo: int = 100, n_hi: int = 244,
+def zlevel_ensemble(seed: int = 0, n_members: int = 16, n_lo: int = 100, n_hi: int = 244,
             dz: float = 5.0, n_min: int = 5, n_max: int = 60, with_fields: bool = True) -> Workload:
     """Batched form: independently seeded members (member m uses seed 1000 + m)
     of n ~ U{n_lo..n_hi} split squares (about 20k-120k triangles each), flat
     z-levels every dz metres, column depth h_c = 25 + 275 g(x, y) at the
     centroid (g a seeded smooth field in [0, 1]), layer count
     clamp(ceil(h_c/dz), n_min, n_max); stair-step bottom (steps are walls).
-    Four fields as in config2 (temperature linear in depth over 300 m)."""
+    Four fields as in four_field_ocean (temperature linear in depth over 300 m)."""
     parts = []
     for m in range(n_members):
         ms = 1000 + seed * 100 + m
@@ -383,7 +383,7 @@ def config4(seed: int = 0, n_members: int = 16, n_lo: int = 100, n_hi: int = 244
         T0 = np.zeros((4,) + z.shape)
     lvl = np.arange(n_max, dtype=np.float64)
     kappa = 10.0 ** (-2.0 - 3.0 * lvl / (n_max - 1))
-    return Workload("config4", vxy, tri, nbr, nl, zl, U, T0, kappa=kappa,
+    return Workload("zlevel_ensemble", vxy, tri, nbr, nl, zl, U, T0, kappa=kappa,
                     dt=cfl_dt(vxy, tri, umax=umax), t_ext=np.array([0.0, 0.0, 17.5, 35.0]),
                     n_steps=50, member_tri_off=moff)
 
@@ -391,7 +391,7 @@ def config4(seed: int = 0, n_members: int = 16, n_lo: int = 100, n_hi: int = 244
 def small_ensemble(seed: int = 0, n_members: int = 3, n_lo: int = 6, n_hi: int = 10,
                    n_fields: int = 2) -> Workload:
     """A few small z-level members (test-sized batched form)."""
-    w = config4(seed=seed, n_members=n_members, n_lo=n_lo, n_hi=n_hi, dz=10.0, n_min=2, n_max=12)
+    w = zlevel_ensemble(seed=seed, n_members=n_members, n_lo=n_lo, n_hi=n_hi, dz=10.0, n_min=2, n_max=12)
     rng = np.random.default_rng([seed, 8])
     T0 = 1.0 + rng.uniform(-0.5, 0.5, size=(n_fields, 6, w.n_prisms))
     return Workload("ensemble", w.vxy, w.tri, w.nbr, w.nlayers, w.zlev, w.U, T0,
