@@ -187,8 +187,15 @@ def mass_matrix(mesh: PrismMesh, prisms=None):
 # ---------------------------------------------------------------------------
 
 def _upwind(un, tin, tout):
-    """Fhat = 1/2 u_n (T_in + T_out) + 1/2 |u_n| (T_in - T_out)."""
+    """Fhat = 1/2 u_n (T_in + T_out) + 1/2 |u_n| (T_in - T_out), at one
+    quadrature point: the upwind side is chosen point by point."""
     return 0.5 * un * (tin + tout) + 0.5 * np.abs(un) * (tin - tout)
+
+
+def _mean_trace(uin, uout):
+    """{U} = (U_in + U_out) / 2, the velocity whose normal component u_n the
+    upwind flux uses on a face (U_out = U_in on an open boundary)."""
+    return 0.5 * (uin + uout)
 
 
 class _Chunk:
@@ -273,7 +280,8 @@ def lateral_flux_term(mesh, U, T, t_ext, prisms):
                 uin = np.einsum("cin,i->cn", g.Us, phi_in)
                 tout = np.where(live[None], np.einsum("fin,ni->fn", To_nodes, phi_out), text)
                 uout = np.where(live[None], np.einsum("cin,ni->cn", Uo_nodes, phi_out), uin)
-                un = 0.5 * ((uin[0] + uout[0]) * nx + (uin[1] + uout[1]) * ny)
+                ub = _mean_trace(uin, uout)
+                un = ub[0] * nx + ub[1] * ny
                 dS = ws * wz * Le * 0.5 * ((1.0 - s) * dz_a + s * dz_b)
                 fl = _upwind(un, tin, tout) * dS
                 fl[:, wall] = 0.0
@@ -307,14 +315,14 @@ def horizontal_flux_term(mesh, U, T, t_ext, prisms):
         uin = np.einsum("cin,i->cn", g.Us, phi_top)
         tout = np.where(has_above[None], np.einsum("fin,i->fn", T[:, :, pa], phi_bot), text)
         uout = np.where(has_above[None], np.einsum("cin,i->cn", U[:, :, pa], phi_bot), uin)
-        ub = 0.5 * (uin + uout)
+        ub = _mean_trace(uin, uout)
         un = (ub[2] - ub[0] * zt_x - ub[1] * zt_y) * g.Jh * wt
         out += phi_top[None, :, None] * _upwind(un, tin, tout)[:, None, :]
         tin = np.einsum("fin,i->fn", g.Ts, phi_bot)
         uin = np.einsum("cin,i->cn", g.Us, phi_bot)
         tout = np.where(has_below[None], np.einsum("fin,i->fn", T[:, :, pb], phi_top), text)
         uout = np.where(has_below[None], np.einsum("cin,i->cn", U[:, :, pb], phi_top), uin)
-        ub = 0.5 * (uin + uout)
+        ub = _mean_trace(uin, uout)
         un = -(ub[2] - ub[0] * zb_x - ub[1] * zb_y) * g.Jh * wt
         out += phi_bot[None, :, None] * _upwind(un, tin, tout)[:, None, :]
     return out
