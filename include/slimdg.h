@@ -317,8 +317,8 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
  * column, D x = F with D the block matrix the paper prints for a 3-layer
  * column, continued to the column's depth -- 1/2 times 3x3 blocks that are
  * multiples of M_h = J_h/24 [2 1 1; 1 2 1; 1 1 2]:
- *   SDG_DV_VU (D_vu, Algorithm 1): per layer l, top rows  2M x_bot(l-1) - M x_top(l) - M x_bot(l),
- *                                               bottom rows M x_top(l) - M x_bot(l);
+ *   SDG_DV_VU (D_vu): per layer l, top rows  2M x_bot(l-1) - M x_top(l) - M x_bot(l),
+ *                                  bottom rows M x_top(l) - M x_bot(l);
  *             the discrete dx/dz = f with x = 0 at the surface, solved top-down;
  *   SDG_DV_VD (D_vd): per layer l, top rows    M x_top(l) - M x_bot(l),
  *                                  bottom rows M x_top(l) + M x_bot(l) - 2M x_top(l+1);

@@ -1,18 +1,25 @@
 // Matrix-free column solvers of the two vertical-derivative systems of the
 // paper's section 2.3: D_vu x = F (the horizontal pressure gradient system,
-// solved from the surface down as in Algorithm 1) and D_vd x = F (the
-// vertical velocity system, solved from the seabed up).
+// integrated from the surface down) and D_vd x = F (the vertical velocity
+// system, integrated from the seabed up).
 //
-// Both matrices are 1/2 times a pattern of 3x3 blocks that are multiples of
-// the 2D mass matrix M_h = J_h/24 [2 1 1; 1 2 1; 1 1 2], so with f = M_h^-1 F
-// per face triple the solve is a running sum over layers:
-//   D_vu (layers from the surface):  s += f_top + f_bot;  x_top = 2 f_bot - s;  x_bot = -s
-//   D_vd (layers from the seabed):   s += f_top + f_bot;  x_top = s;            x_bot = s - 2 f_top
-// and M_h^-1 F_i = (6/J_h) (4 F_i - (F_0 + F_1 + F_2)).
+// Derivation from the printed block rows.  Both matrices are (1/2) P (x) M_h
+// with P a pattern of small integers and M_h = J_h/24 [2 1 1; 1 2 1; 1 1 2],
+// so D x = F is P x = 2 f per node triple with f = M_h^-1 F, and
+// M_h^-1 F_i = (6/J_h) (4 F_i - (F_0 + F_1 + F_2)).  Per layer l, with t and b
+// the top- and bottom-face node triples:
+//   D_vu:  x_t(l) - x_b(l) = 2 f_b(l)  and  2 x_b(l-1) - x_t(l) - x_b(l) = 2 f_t(l),
+//          hence x_b(l) = x_b(l-1) - (f_t(l) + f_b(l)) from x_b(-1) = 0 at the
+//          surface, and x_t(l) = x_b(l) + 2 f_b(l);
+//   D_vd:  x_t(l) - x_b(l) = 2 f_t(l)  and  x_t(l) + x_b(l) - 2 x_t(l+1) = 2 f_b(l),
+//          hence x_t(l) = x_t(l+1) + (f_t(l) + f_b(l)) from x_t(N) = 0 at the
+//          seabed, and x_b(l) = x_t(l) - 2 f_t(l).
+// Each lane carries one value per node of its column: the solution on the
+// face the sweep crosses into the next layer (x_b going down, x_t going up).
 //
 // One wavefront per cell, one lane per column: every layer's six values per
 // component are six coalesced 64-wide loads.  The loads do not depend on the
-// running sum, so the loop keeps kAhead layers in flight ahead of the one it
+// carried value, so the loop keeps kAhead layers in flight ahead of the one it
 // finishes.  Values are read before they are written, by the same lane, so F
 // and x may be the same buffer.
 #include "internal.h"
@@ -60,11 +67,13 @@ __global__ __launch_bounds__(64) void column_dv_kernel(DevMesh m, const T* F, T*
     load_layer(q[i], F, SL, base + (int64_t)l * kCell, i < D && l < N);
   }
 
-  C s[NC][3];
+  // solution on the face shared with the previously visited layer (zero at
+  // the surface for D_vu, at the seabed for D_vd)
+  C xf[NC][3];
 #pragma unroll
   for (int k = 0; k < NC; ++k)
 #pragma unroll
-    for (int n = 0; n < 3; ++n) s[k][n] = (C)0;
+    for (int n = 0; n < 3; ++n) xf[k][n] = (C)0;
 
   for (int i0 = 0; i0 < D; i0 += kAhead) {
 #pragma unroll
@@ -89,9 +98,16 @@ __global__ __launch_bounds__(64) void column_dv_kernel(DevMesh m, const T* F, T*
           for (int n = 0; n < 3; ++n) {
             const C ft = minv * ((C)4 * v[n] - st);
             const C fb = minv * ((C)4 * v[3 + n] - sb);
-            s[k][n] += ft + fb;
-            const C xt = DOWN ? (C)2 * fb - s[k][n] : s[k][n];
-            const C xb = DOWN ? -s[k][n] : s[k][n] - (C)2 * ft;
+            C xt, xb;
+            if (DOWN) {
+              xb = xf[k][n] - (ft + fb);
+              xt = xb + (C)2 * fb;
+              xf[k][n] = xb;
+            } else {
+              xt = xf[k][n] + (ft + fb);
+              xb = xt - (C)2 * ft;
+              xf[k][n] = xt;
+            }
             X[(k * 6 + n) * SL + slot] = (T)xt;
             X[(k * 6 + 3 + n) * SL + slot] = (T)xb;
           }

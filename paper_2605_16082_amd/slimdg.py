@@ -257,7 +257,7 @@ class SlimDG:
                              f"on {self.device}, got {t.dtype} {tuple(t.shape)} on {t.device}")
 
     # -- state ---------------------------------------------------------------
-    def set_params(self, dt: float, t_ext=None, penalty_eta: float = 4.0, w_is_zero: bool = True,
+    def set_params(self, dt: float, t_ext=None, penalty_eta: float = 4.0, w_is_zero: bool = False,
                    check_finite: bool = False, time_scheme: int = SDG_SCHEME_SSPRK3_LIE,
                    okubo_scale: float = 0.0):
         text = np.zeros(self.n_fields) if t_ext is None else np.ascontiguousarray(t_ext, dtype=np.float64)

@@ -2,8 +2,8 @@
 
 Routes other than the oracle's own assembly:
 * the 3-layer matrices as printed in the paper (golden fixtures);
-* the paper's own top-down solver for D_vu (Algorithm 1), restated here from
-  its description, against the dense solve;
+* the solution against the system assembled directly from those printed
+  3-layer matrices and the printed M_h (residual);
 * the continuous problems behind the two systems (dx/dz = f with x = 0 at the
   surface for D_vu and at the seabed for D_vd): right-hand sides computed by
   quadrature of the weak form, and the exact integrals of f, which the
@@ -52,32 +52,26 @@ def test_printed_mass_matrix():
     assert np.allclose(A[:3, :3], -0.5 * _load("mass_2d.txt") * jh / 24.0, atol=1e-15)
 
 
-def _algorithm1(jh, F):
-    """Top-down solver of the paper's Algorithm 1 for one column: F (N, 6)."""
-    Minv = np.linalg.inv(jh / 24.0 * (np.ones((3, 3)) + np.eye(3)))
-    s = np.zeros(3)
-    out = np.empty_like(F)
-    for l in range(F.shape[0]):
-        r = np.concatenate([Minv @ F[l, :3], Minv @ F[l, 3:]])
-        s = s + r[:3] + r[3:]
-        out[l, :3] = -s + 2.0 * r[3:]
-        out[l, 3:] = -s
-    return out
-
-
-def test_algorithm1_equals_dense_vu():
-    vxy, tri, nl = _ragged()
+def test_solution_satisfies_printed_system():
+    """On 3-layer columns the solution satisfies the system assembled from the
+    printed matrices themselves: (1/2) pattern (x) M_h, both from the golden
+    fixtures, with no use of the oracle's own pattern or assembly."""
+    w = W.tiny(seed=4, n=3, n_layers=3)
+    nl = w.nlayers
+    assert np.all(nl == 3)
     rng = np.random.default_rng(11)
     F = rng.standard_normal((2, 6, int(nl.sum())))
-    x = CD.dv_solve("vu", vxy, tri, nl, F)
-    p = vxy[tri]
-    jh = _jh(p)
-    off = np.concatenate([[0], np.cumsum(nl)])
-    for c in range(len(nl)):
-        for k in range(2):
-            ref = _algorithm1(jh[c], F[k, :, off[c]:off[c + 1]].T)
-            got = x[k, :, off[c]:off[c + 1]].T
-            assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref)), (c, k)
+    jh = _jh(w.vxy[w.tri])
+    mh = _load("mass_2d.txt") / 24.0
+    for kind in ("vu", "vd"):
+        x = CD.dv_solve(kind, w.vxy, w.tri, nl, F)
+        printed = _load(f"column_dv_{kind}_3layer.txt")
+        for c in range(len(nl)):
+            D = 0.5 * np.kron(printed, jh[c] * mh)
+            for k in range(2):
+                xs = x[k, :, 3 * c:3 * c + 3].T.ravel()      # (layer, node)
+                fs = F[k, :, 3 * c:3 * c + 3].T.ravel()
+                assert np.max(np.abs(D @ xs - fs)) <= 1e-12 * np.max(np.abs(fs)), (kind, c, k)
 
 
 # -- the continuous problems -------------------------------------------------
