@@ -146,6 +146,11 @@ def mass_matrix_global(mesh: PrismMesh) -> sp.csr_matrix:
     return sp.block_diag(list(Mp), format="csr")
 
 
+def mass_inverse_global(mesh: PrismMesh) -> sp.csr_matrix:
+    """Block-diagonal M^-1 (6P x 6P): each prism's 6x6 mass block inverted."""
+    return sp.block_diag(list(np.linalg.inv(mass_matrix(mesh))), format="csr")
+
+
 def vertical_matrix_global(mesh: PrismMesh, kappa, eta=4.0) -> sp.csr_matrix:
     """Vertical diffusion A (6P x 6P) assembled column by column."""
     P = mesh.P
@@ -183,10 +188,14 @@ def forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
     return xs
 
 
-def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
+def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None, return_scale=False):
     """(J, dJ/dT0 of shape (F, 6, P), dJ/dkappa of shape (len(kappa),)).
     With per-column kappa_h the explicit operator also holds the horizontal
-    diffusion matrix D (linear, so it adds D to R_lin)."""
+    diffusion matrix D (linear, so it adds D to R_lin).
+
+    With return_scale, also the size of the sum behind each dJ/dkappa_l:
+    sum_n dt |mu_n|^T |A_l| |x^{n+1}|, the sum of its terms' magnitudes, which
+    bounds how far rounding in the terms can move the (cancelling) total."""
     kappa = np.asarray(kappa, dtype=np.float64)
     F = T0.shape[0]
     xs = forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta, kappa_h)
@@ -195,7 +204,7 @@ def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h
     if kappa_h is not None:
         from .horizontal_diffusion import horizontal_diffusion_matrix
         R = (R + horizontal_diffusion_matrix(mesh, kappa_h, eta)).tocsr()
-    Minv_R = sp.csr_matrix(spla.spsolve(M.tocsc(), R.tocsc()))
+    Minv_R = (mass_inverse_global(mesh) @ R).tocsr()     # L = M^-1 R, M block-diagonal
     Lt = Minv_R.T.tocsr()                                   # L^T
     A = vertical_matrix_global(mesh, kappa, eta)
     K_T = (M - dt * A).T.tocsc()
@@ -204,21 +213,27 @@ def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h
         e = np.zeros_like(kappa)
         e[l] = 1.0
         A_l.append(vertical_matrix_global(mesh, e, eta))
+    absA_l = [abs(a) for a in A_l] if return_scale else None
     xN = _flat(xs[-1])
     J = float(np.sqrt(np.sum(xN * (M @ xN))))
     lam = (M @ xN) / J
     dk = np.zeros_like(kappa)
+    dk_abs = np.zeros_like(kappa)
     for n in range(n_steps - 1, -1, -1):
         mu = spla.spsolve(K_T, lam).reshape(lam.shape)
         x1 = _flat(xs[n + 1])
         for l in range(len(kappa)):
             dk[l] += dt * np.sum(mu * (A_l[l] @ x1))
+            if return_scale:
+                dk_abs[l] += dt * np.sum(np.abs(mu) * (absA_l[l] @ np.abs(x1)))
         y = M @ mu
         # P'^T y = y + dt L^T y + (dt L^T)^2 y / 2 + (dt L^T)^3 y / 6
         t1 = dt * (Lt @ y)
         t2 = dt * (Lt @ t1) / 2.0
         t3 = dt * (Lt @ t2) / 3.0
         lam = y + t1 + t2 + t3
+    if return_scale:
+        return J, _unflat(lam, F), dk, dk_abs
     return J, _unflat(lam, F), dk
 
 
@@ -226,7 +241,7 @@ def objective_after_steps(mesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0) -> fl
     return objective(mesh, forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta)[-1])
 
 
-def gradient_imex(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
+def gradient_imex(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None, return_scale=False):
     """(J, dJ/dT0, dJ/dkappa) for n_steps of the split-IMEX step
     (``split_imex.imex_step``), by reverse-mode differentiation of its two
     steps with h = dt/2 and G = M^-1 (R + A):
@@ -238,7 +253,8 @@ def gradient_imex(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, ka
         dJ/dkappa_l += dt lambda'^T M^-1 A_l x_h + h mu^T A_l x_h
 
     with the same assembled operators as ``gradient`` (R includes the
-    horizontal diffusion matrix when kappa_h is given)."""
+    horizontal diffusion matrix when kappa_h is given).  return_scale adds the
+    sums of the kappa terms' magnitudes, as in ``gradient``."""
     from .split_imex import imex_step
     kappa = np.asarray(kappa, dtype=np.float64)
     F = T0.shape[0]
@@ -266,6 +282,7 @@ def gradient_imex(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, ka
     J = float(np.sqrt(np.sum(xN * (M @ xN))))
     lam = (M @ xN) / J
     dk = np.zeros_like(kappa)
+    dk_abs = np.zeros_like(kappa)
     for n in range(n_steps - 1, -1, -1):
         Minv_lam = spla.spsolve(M, lam).reshape(lam.shape)
         mu = spla.spsolve(Kh_T, dt * (RA_T @ Minv_lam)).reshape(lam.shape)
@@ -273,5 +290,10 @@ def gradient_imex(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, ka
         for l in range(len(kappa)):
             Ax = A_l[l] @ x_h
             dk[l] += dt * np.sum(Minv_lam * Ax) + h * np.sum(mu * Ax)
+            if return_scale:
+                aAx = abs(A_l[l]) @ np.abs(x_h)
+                dk_abs[l] += dt * np.sum(np.abs(Minv_lam) * aAx) + h * np.sum(np.abs(mu) * aAx)
         lam = lam + MhR_T @ mu
+    if return_scale:
+        return J, _unflat(lam, F), dk, dk_abs
     return J, _unflat(lam, F), dk

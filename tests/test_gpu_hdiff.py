@@ -184,15 +184,17 @@ def test_adjoint_with_horizontal_diffusion_matches_oracle(name):
     xN = P.TracerSteps.apply(T0, kap, s, n_steps, 2)
     J = P.MNorm.apply(xN, s)
     J.backward()
-    Jr, gTr, gkr = OA.gradient(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, n_steps, w.penalty, kappa_h=kh)
+    Jr, gTr, gkr, gka = OA.gradient(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, n_steps, w.penalty, kappa_h=kh,
+                                    return_scale=True)
     gT = s.gather(T0.grad)
     gk = kap.grad.detach().cpu().numpy()
     eT = np.abs(gT - gTr).max() / np.abs(gTr).max()
-    ek = np.abs(gk - gkr).max() / np.abs(gkr).max()
-    print(name, "J", float(J.detach()), Jr, "dT0", eT, "dkappa", ek)
+    ek = (np.abs(gk - gkr) / gka).max()
+    print(name, "J", float(J.detach()), Jr, "dT0", eT, "dkappa / term magnitudes", ek)
     assert abs(float(J.detach()) - Jr) <= 1e-12 * abs(Jr)
     assert Jr < 2.0 * OA.objective(m, w.T0)                         # a stable run
-    assert eT <= 1e-11 and ek <= 1e-9      # see test_adjoint_gradient_matches_oracle
+    # dJ/dkappa_l is a cancelling sum: bar 1e-12 of its terms' magnitudes
+    assert eT <= 1e-12 and ek <= 1e-12
 
 
 def test_argument_errors():
