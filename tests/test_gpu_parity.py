@@ -60,6 +60,12 @@ def case(name):
                            w.kappa[:1], w.dt, np.array([0.4]))
         elif name == "deep_ragged":
             w = W.ragged(seed=3, n=9, n_min=1, n_max=37, depth_max=190.0, n_fields=3)
+        elif name == "deep_ragged_w":
+            # 1-37 layers (walks of several segments) with a discontinuous
+            # velocity whose vertical component is read
+            w = W.ragged(seed=3, n=9, n_min=1, n_max=37, depth_max=190.0, n_fields=3)
+            w.U = _random_velocity(w, seed=6)
+            w.w_is_zero = False
         else:
             raise KeyError(name)
         _CASES[name] = (w, O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev))
@@ -270,3 +276,44 @@ def test_four_field_ocean_sampled_parity(big, precision, shape):
     err = rel_err(got, ref_full[:, :, pr])
     print("four_field_ocean solve", err)
     assert np.all(err <= (TOL64 if precision == P.SDG_FP64 else 5e-5)), err
+
+
+WALK_SHAPES = [(8, 1, 0), (8, 1, 1), (12, 1, 0), (12, 0, 1), (16, 1, 0), (16, 1, 1), (32, 1, 0), (32, 0, 1)]
+
+
+@pytest.mark.parametrize("name", ["wnonzero", "deep_ragged_w"])
+def test_walk_shapes_with_vertical_velocity(name):
+    """The column walk with the vertical velocity read (w != 0, discontinuous
+    U): rhs_3d, the three SSP-RK3 stages and a split-IMEX step (whose first
+    launch stores a second output) in walk shapes of 8-32 layers, with and
+    without the persistent grid, against the oracle and bitwise against the
+    2-layer one-thread-per-prism tile."""
+    from oracle.split_imex import imex_step
+    w, m = case(name)
+    assert not w.w_is_zero and np.abs(w.U[2]).max() > 0
+    s, U, kappa, state = upload(w)
+    imex, _, _, istate = P.from_workload(w, P.SDG_FP64, time_scheme=P.SDG_SCHEME_SPLIT_IMEX)
+    rng = np.random.default_rng([13, len(name)])
+    Ts_np = w.T0 + 0.1 * rng.standard_normal(w.T0.shape)
+    Ts = s.scatter(Ts_np)
+    refs = [O.explicit_operator(m, w.U, Ts_np, w.t_ext)]
+    refs += [O.rk_stage(m, w.U, k, w.T0, Ts_np, w.dt, w.t_ext) for k in range(3)]
+    refs.append(imex_step(m, w.U, w.kappa, w.T0, w.dt, w.t_ext, w.penalty))
+    base = None
+    for shape in [(2, 1, 0)] + WALK_SHAPES:
+        s.set_tuning(*shape)
+        imex.set_tuning(*shape)
+        outs = [s.rhs_3d(Ts)] + [s.rk_stage(k, state, Ts) for k in range(3)]
+        imex.scatter(w.T0, out=istate)
+        imex.step(1)
+        s.sync()
+        imex.sync()
+        got = [s.gather(o) for o in outs] + [imex.gather(istate)]
+        for k, (g, r) in enumerate(zip(got, refs)):
+            err = rel_err(g, r)
+            assert np.all(err <= TOL64), (shape, k, err)
+        if base is None:
+            base = got
+        else:
+            for k, (g, b) in enumerate(zip(got, base)):
+                assert np.array_equal(g, b), (shape, k)
