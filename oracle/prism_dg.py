@@ -448,13 +448,15 @@ def column_system(mesh: PrismMesh, kappa, dt, c, eta=4.0):
     return Mc - dt * vertical_diffusion_matrix(mesh, kappa, c, eta), Mc
 
 
-def implicit_solve(mesh: PrismMesh, kappa, dt, Tstar, eta=4.0, columns=None):
+def implicit_solve(mesh: PrismMesh, kappa, dt, Tstar, eta=4.0, columns=None, out=None):
     """Solve (M - dt A) T^{n+1} = M T* column by column with a dense solver.
 
-    Tstar (F, 6, P).  Returns a copy with the selected columns replaced.
+    Tstar (F, 6, P).  Returns a copy with the selected columns replaced, or,
+    given ``out`` (F, 6, P), writes the selected columns there and returns it.
     Columns with the same layer count are solved as one batch.
     """
-    out = np.array(Tstar, dtype=np.float64, copy=True)
+    if out is None:
+        out = np.array(Tstar, dtype=np.float64, copy=True)
     cols = np.arange(mesh.C) if columns is None else np.asarray(columns, dtype=np.int64)
     F = Tstar.shape[0]
     for N in np.unique(mesh.nl[cols]):

@@ -27,10 +27,12 @@ from .horizontal_diffusion import horizontal_diffusion_term
 from .prism_dg import PrismMesh, _column_masses, advective_residual, vertical_diffusion_matrices
 
 
-def _column_groups(mesh: PrismMesh, chunk_bytes: int = 1 << 25):
-    """Columns grouped by layer count, in chunks of bounded dense size."""
-    for N in np.unique(mesh.nl):
-        group = np.nonzero(mesh.nl == N)[0]
+def _column_groups(mesh: PrismMesh, chunk_bytes: int = 1 << 25, columns=None):
+    """Columns (all, or the given ones) grouped by layer count, in chunks of
+    bounded dense size."""
+    cols = np.arange(mesh.C) if columns is None else np.asarray(columns, dtype=np.int64)
+    for N in np.unique(mesh.nl[cols]):
+        group = cols[mesh.nl[cols] == N]
         step_c = max(1, chunk_bytes // (8 * 36 * int(N) * int(N)))
         for i in range(0, len(group), step_c):
             g = group[i:i + step_c]
@@ -57,33 +59,43 @@ def vertical_diffusion_apply(mesh: PrismMesh, kappa, T, eta=4.0):
     return out
 
 
-def _residual(mesh, U, T, t_ext, kappa_h, eta):
-    R = advective_residual(mesh, U, T, t_ext)
+def _residual(mesh, U, T, t_ext, kappa_h, eta, prisms=None):
+    R = advective_residual(mesh, U, T, t_ext, prisms)
     if kappa_h is not None:
-        R = R + horizontal_diffusion_term(mesh, kappa_h, T, eta)
+        R = R + horizontal_diffusion_term(mesh, kappa_h, T, eta, prisms)
     return R
+
+
+def imex_half_step(mesh: PrismMesh, kappa, T0, R0, dt, eta, out, columns=None):
+    """Step 1 on the selected columns: (M - dt/2 A) x_h = M x_0 + dt/2 R(x_0),
+    with R0 = R(x_0) given; x_h written into out."""
+    for _, g, ps in _column_groups(mesh, columns=columns):
+        Mc = _column_masses(mesh, g)
+        A = vertical_diffusion_matrices(mesh, kappa, g, eta)
+        rhs = Mc @ _to_columns(T0, ps) + 0.5 * dt * _to_columns(R0, ps)
+        _from_columns(np.linalg.solve(Mc - 0.5 * dt * A, rhs), ps, out)
+    return out
+
+
+def imex_full_step(mesh: PrismMesh, kappa, T0, Th, Rh, dt, eta, out, columns=None):
+    """Step 2 on the selected columns: M x_1 = M x_0 + dt (R(x_h) + A x_h),
+    with Rh = R(x_h) given; x_1 written into out."""
+    for _, g, ps in _column_groups(mesh, columns=columns):
+        Mc = _column_masses(mesh, g)
+        A = vertical_diffusion_matrices(mesh, kappa, g, eta)
+        incr = np.linalg.solve(Mc, _to_columns(Rh, ps) + A @ _to_columns(Th, ps))
+        _from_columns(_to_columns(T0, ps) + dt * incr, ps, out)
+    return out
 
 
 def imex_step(mesh: PrismMesh, U, kappa, T0, dt, t_ext, eta=4.0, return_half=False, kappa_h=None):
     """One split-IMEX step from T0 (F, 6, P); returns T1 (and x_h).  With
     per-column kappa_h, R also holds the (explicit) horizontal diffusion."""
     T0 = np.asarray(T0, dtype=np.float64)
-    # step 1: (M - dt/2 A) x_h = M x_0 + dt/2 R(x_0)
     R0 = _residual(mesh, U, T0, t_ext, kappa_h, eta)
-    Th = np.empty_like(T0)
-    for _, g, ps in _column_groups(mesh):
-        Mc = _column_masses(mesh, g)
-        A = vertical_diffusion_matrices(mesh, kappa, g, eta)
-        rhs = Mc @ _to_columns(T0, ps) + 0.5 * dt * _to_columns(R0, ps)
-        _from_columns(np.linalg.solve(Mc - 0.5 * dt * A, rhs), ps, Th)
-    # step 2: M x_1 = M x_0 + dt (R(x_h) + A x_h)
+    Th = imex_half_step(mesh, kappa, T0, R0, dt, eta, np.empty_like(T0))
     Rh = _residual(mesh, U, Th, t_ext, kappa_h, eta)
-    T1 = np.empty_like(T0)
-    for _, g, ps in _column_groups(mesh):
-        Mc = _column_masses(mesh, g)
-        A = vertical_diffusion_matrices(mesh, kappa, g, eta)
-        incr = np.linalg.solve(Mc, _to_columns(Rh, ps) + A @ _to_columns(Th, ps))
-        _from_columns(_to_columns(T0, ps) + dt * incr, ps, T1)
+    T1 = imex_full_step(mesh, kappa, T0, Th, Rh, dt, eta, np.empty_like(T0))
     if return_half:
         return T1, Th
     return T1
