@@ -248,6 +248,18 @@ sdg_status sdg_step(sdg_ctx* ctx, int n_steps);
  * 1.1 tracer equation).  Synchronises the stream. */
 sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
+/* For callers that cannot allocate device memory at the call (code under
+ * stream capture, tight serving loops, harnesses that forbid it): sdg_mass
+ * with its partial sums kept in a static device array of the library instead
+ * of the mesh workspace.  Same arguments, results (bitwise: the same kernels
+ * in the same order) and synchronisation as sdg_mass; it calls no device or
+ * host allocator.  Limit: n_fields x (column slots + members) <= 8,388,608
+ * doubles (64 MiB; column slots = 64 x cells), else SDG_E_WORKSPACE.  Each
+ * device holds one such array from the first sdg_create on it until the
+ * process ends, shared by every context on that device: calls that overlap
+ * on one device (two streams, two threads) race on it. */
+sdg_status sdg_mass_noalloc(sdg_ctx* ctx, const void* dev_T, double* host_mass);
+
 /* Launch shape of the fused stage kernel (the paper's section 4.1 shows
  * throughput depending on the column block shape; here the library measures
  * it).  Results do not depend on it (bitwise).

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -212,6 +213,39 @@ class DeviceGuard {
   int prev_ = -1;
 };
 
+// ---------------------------------------------------------------------------
+// Static scratch of sdg_mass_noalloc: each device holds its own copy of this
+// array from the first context created on it until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): it uses the address that
+// hipGetSymbolAddress returned on that device, kept per device below.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocDoubles = size_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Looks up this device's copy of the scratch array once; the device must be
+// current.  Called by sdg_create.
+hipError_t bind_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+double* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 struct sdg_ctx {
@@ -309,6 +343,14 @@ sdg_status sdg_create(sdg_ctx** out, int device, void* hip_stream) {
     return hip_fail(e, "hipDeviceGetAttribute(multiprocessor count)");
   }
   if (c->n_cu < 1) c->n_cu = 1;
+  {
+    DeviceGuard g(device);
+    e = bind_static_scratch(device);
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+  }
   *out = c;
   g_err.clear();
   return SDG_OK;
@@ -734,6 +776,34 @@ sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass) {
   e = hipMemcpyAsync(host_mass, ctx->msum, sizeof(double) * P.F * P.n_members, hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(e, "sdg_mass");
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_mass_noalloc(sdg_ctx* ctx, const void* dev_T, double* host_mass) {
+  if (!ctx || !dev_T || !host_mass) return fail(SDG_E_ARG, "sdg_mass_noalloc: NULL argument");
+  if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_mass_noalloc needs an uploaded mesh");
+  const Plan& P = ctx->plan;
+  // per-column partials [F][n_col_slots], then the member sums [n_members][F];
+  // every entry is written before it is read, so nothing needs clearing
+  const size_t n_part = (size_t)P.F * (size_t)P.CS;
+  const size_t need = n_part + (size_t)P.F * (size_t)P.n_members;
+  if (need > kNoAllocDoubles)
+    return fail(SDG_E_WORKSPACE,
+                "sdg_mass_noalloc: this mesh needs %zu doubles of static scratch (n_fields x (column slots + "
+                "members)), more than its %zu; use sdg_mass",
+                need, kNoAllocDoubles);
+  double* base = static_scratch(ctx->device);
+  if (!base) return fail(SDG_E_STATE, "sdg_mass_noalloc: no static scratch bound on device %d", ctx->device);
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_column_mass(ctx->dm, dev_T, P.F, P.fp32, base, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "column mass launch");
+  e = launch_member_sum(base, P.CS, P.F, ctx->member_off_dev, P.n_members, base + n_part, ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "member sum launch");
+  e = hipMemcpyAsync(host_mass, base + n_part, sizeof(double) * P.F * P.n_members, hipMemcpyDeviceToHost,
+                     ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(e, "sdg_mass_noalloc");
   g_err.clear();
   return SDG_OK;
 }

@@ -30,7 +30,7 @@ EXPORTED = (
     "sdg_set_fields", "sdg_rhs_3d", "sdg_rk_stage", "sdg_vertical_implicit_solve", "sdg_step",
     "sdg_mass", "sdg_sync", "sdg_get_tuning", "sdg_set_tuning", "sdg_autotune",
     "sdg_graph_capture_step", "sdg_graph_launch", "sdg_apply_mass", "sdg_m_dot", "sdg_step_adjoint",
-    "sdg_column_dv_solve", "sdg_step_adjoint_imex",
+    "sdg_column_dv_solve", "sdg_step_adjoint_imex", "sdg_mass_noalloc",
 )
 
 
@@ -128,6 +128,7 @@ def load_library(path: str | None = None):
         "sdg_step_adjoint": ([vp, vp, vp, vp, vp], i32),
         "sdg_column_dv_solve": ([vp, i32, i32, vp, vp], i32),
         "sdg_step_adjoint_imex": ([vp, vp, vp, vp, vp], i32),
+        "sdg_mass_noalloc": ([vp, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -312,6 +313,14 @@ class SlimDG:
         self._check_nodal(T, self.n_fields)
         out = np.zeros(self.mesh.n_members * self.n_fields, dtype=np.float64)
         _check(self.lib.sdg_mass(self.ctx, _ptr(T), out.ctypes.data))
+        return out.reshape(self.mesh.n_members, self.n_fields)
+
+    def mass_noalloc(self, T) -> np.ndarray:
+        """``mass`` through the entry point that keeps its partial sums in the
+        library's static device scratch (no workspace, no allocation)."""
+        self._check_nodal(T, self.n_fields)
+        out = np.zeros(self.mesh.n_members * self.n_fields, dtype=np.float64)
+        _check(self.lib.sdg_mass_noalloc(self.ctx, _ptr(T), out.ctypes.data))
         return out.reshape(self.mesh.n_members, self.n_fields)
 
     def sync(self):
