@@ -276,6 +276,9 @@ struct sdg_ctx {
   void* stage_a = nullptr;
   void* stage_b = nullptr;
   double* scratch = nullptr;
+  // the solve scratch holds the block-Thomas factors of (kappa, efac_dt, eta)
+  bool efac_valid = false;
+  double efac_dt = 0.0;
   // state set by the caller
   bool have_params = false;
   double dt = 0.0, eta = 4.0;
@@ -383,6 +386,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   ctx->have_params = false;   // t_ext and the horizontal diffusivity belong to the mesh
   ctx->kh_scale = 0.0;
   ctx->graph_valid = false;
+  ctx->efac_valid = false;
   ctx->U = nullptr;
   ctx->kappa = nullptr;
   ctx->state = nullptr;
@@ -545,6 +549,7 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
   ctx->w_zero = p->w_is_zero != 0;
   ctx->check_finite = p->check_finite != 0;
   ctx->graph_valid = false;
+  ctx->efac_valid = false;
   ctx->have_params = true;
   g_err.clear();
   return SDG_OK;
@@ -564,6 +569,7 @@ sdg_status sdg_set_diffusivity(sdg_ctx* ctx, const double* dev_kappa) {
   if (!ctx->have_mesh) return fail(SDG_E_STATE, "sdg_set_diffusivity needs an uploaded mesh");
   ctx->kappa = dev_kappa;
   ctx->graph_valid = false;
+  ctx->efac_valid = false;
   g_err.clear();
   return SDG_OK;
 }
@@ -645,7 +651,7 @@ sdg_status enqueue_stage(sdg_ctx* ctx, int stage, const void* Tn, const void* Ts
   return SDG_OK;
 }
 
-sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt, hipStream_t strm) {
+SolveArgs solve_args(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt) {
   SolveArgs a{};
   a.m = ctx->dm;
   a.n_fields = ctx->plan.F;
@@ -655,7 +661,30 @@ sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt,
   a.scratch = ctx->scratch;
   a.dt = dt;
   a.eta = ctx->eta;
-  hipError_t e = launch_vsolve(a, ctx->plan.fp32, ctx->plan.prec == SDG_FP32, strm);
+  return a;
+}
+
+// The block-Thomas factors for a solve over dt: kept in the solve scratch
+// until kappa, the parameters or the mesh change, or the adjoint's
+// transposed solve reuses the scratch.
+sdg_status ensure_factors(sdg_ctx* ctx, double dt, hipStream_t strm) {
+  if (ctx->efac_valid && ctx->efac_dt == dt) return SDG_OK;
+  hipError_t e = launch_vsolve(solve_args(ctx, nullptr, nullptr, dt), ctx->plan.fp32, ctx->plan.prec == SDG_FP32,
+                               true, strm);
+  if (e != hipSuccess) return hip_fail(e, "column factor launch");
+  ctx->efac_valid = true;
+  ctx->efac_dt = dt;
+  return SDG_OK;
+}
+
+// the solve's dt in a step of the context's scheme
+double step_solve_dt(const sdg_ctx* ctx) { return ctx->scheme == SDG_SCHEME_SPLIT_IMEX ? 0.5 * ctx->dt : ctx->dt; }
+
+sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt, hipStream_t strm) {
+  sdg_status st = ensure_factors(ctx, dt, strm);
+  if (st != SDG_OK) return st;
+  hipError_t e = launch_vsolve(solve_args(ctx, Tstar, Tout, dt), ctx->plan.fp32, ctx->plan.prec == SDG_FP32,
+                               false, strm);
   if (e != hipSuccess) return hip_fail(e, "vertical solve launch");
   return SDG_OK;
 }
@@ -909,8 +938,11 @@ sdg_status sdg_graph_capture_step(sdg_ctx* ctx) {
   hipError_t e = hipSuccess;
   if (!ctx->cap_stream) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "sdg_graph_capture_step: stream");
-  // the captured kernels must not overtake work already queued on the
-  // context stream: capture starts after it has drained
+  // the factors are computed outside the graph (sdg_graph_launch keeps
+  // them current); the captured kernels must not overtake work already
+  // queued on the context stream: capture starts after it has drained
+  st = ensure_factors(ctx, step_solve_dt(ctx), ctx->stream);
+  if (st != SDG_OK) return st;
   e = hipStreamSynchronize(ctx->stream);
   if (e == hipSuccess) e = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "sdg_graph_capture_step: begin capture");
@@ -938,6 +970,10 @@ sdg_status sdg_graph_launch(sdg_ctx* ctx, int n_steps) {
   if (!ctx->graph_valid) return fail(SDG_E_STATE, "no valid captured step (capture again after any set_* call)");
   if (n_steps < 0) return fail(SDG_E_ARG, "n_steps must be >= 0");
   DeviceGuard g(ctx->device);
+  if (n_steps > 0) {
+    sdg_status st = ensure_factors(ctx, step_solve_dt(ctx), ctx->stream);
+    if (st != SDG_OK) return st;
+  }
   for (int n = 0; n < n_steps; ++n) {
     hipError_t e = hipGraphLaunch(ctx->graph_exec, ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
@@ -1000,6 +1036,7 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   const WgTile* tiles = ctx->tiles[choice];
   const int nt = P.n_tiles[choice];
   hipStream_t s = ctx->stream;
+  ctx->efac_valid = false;   // the transposed solve reuses the solve scratch
   hipError_t e = launch_tsolve(ctx->dm, P.F, static_cast<const double*>(dev_z_next), mu, ctx->kappa,
                                ctx->scratch, ctx->dt, ctx->eta, s);
   if (e != hipSuccess) return hip_fail(e, "transposed solve launch");
@@ -1075,6 +1112,7 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
                            0.0, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, Z1, w, nullptr, 2.0 * h, 0.0, s);
   // mu' = (M - h A^T)^-1 M w;  dJ/dkappa_l += h mu'^T A_l x_h
+  ctx->efac_valid = false;   // the transposed solve reuses the solve scratch
   if (e == hipSuccess) e = launch_tsolve(ctx->dm, P.F, w, mu, ctx->kappa, ctx->scratch, h, ctx->eta, s);
   if (e == hipSuccess && dev_dkappa)
     e = launch_kappa_gradient(ctx->dm, P.F, mu, out, ctx->kpart, ctx->eta, h, dev_dkappa, s);

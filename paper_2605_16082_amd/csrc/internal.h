@@ -86,7 +86,8 @@ struct SolveArgs {
   const void* Tstar;
   void* Tout;
   const double* kappa;   // [max_layers]
-  double* scratch;       // [18 + 6F][n_slots] values of the solve's arithmetic type
+  double* scratch;       // [18 + 6F][n_slots] values of the solve's arithmetic type:
+                         // the kept E_l (18), then y_l (6F)
   double dt;
   double eta;
 };
@@ -117,7 +118,9 @@ hipError_t launch_geometry(const DevMesh& m, double* geo, float* geo32, hipStrea
 hipError_t launch_z32(const DevMesh& m, float* zl32, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, bool fp32, bool w_zero, bool rhs_only,
                         bool read_tn, hipStream_t s);
-hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, hipStream_t s);
+// factor = true: compute and keep the block-Thomas factors E_l for (kappa, dt,
+// eta) in a.scratch (the fields are not read); false: solve with kept factors.
+hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, bool factor, hipStream_t s);
 // Matrix-free D_vu (down = true) / D_vd column solves; fp32_arith only with fp32_state.
 hipError_t launch_column_dv(const DevMesh& m, bool down, int n_comp, const void* F, void* X, bool fp32_state,
                             bool fp32_arith, hipStream_t s);

@@ -22,11 +22,19 @@
 //
 // which is the half-block sparsity drawn in section 2.4.  Block Thomas
 // without pivoting: forward sweep D'_l = D_l - B_l D'_{l-1}^-1 C_{l-1}, with
-// the LU of D'_l shared by all fields; E_l = D'_l^-1 [:, 3:6] and
-// y_l = D'_l^-1 r'_l go to scratch (as 16-byte pairs); back substitution
-// x_l = y_l - E_l (C_l x_{l+1}) recomputes C_l from the levels.  The
-// arithmetic type C is double (the FP64 and FP32-state/FP64-solve forms) or
-// float (the FP32-everywhere form); the scratch then holds values of type C.
+// the LU of D'_l shared by all fields, E_l = D'_l^-1 [:, 3:6] and
+// y_l = D'_l^-1 r'_l; back substitution x_l = y_l - E_l (C_l x_{l+1})
+// recomputes C_l from the levels.
+//
+// E_l depends only on the mesh, kappa, dt and the penalty, not on the
+// fields, so it is computed once for a given (kappa, dt, eta) by a sweep
+// without fields (factor_kernel) and kept in scratch; each solve's forward
+// sweep recomputes it in registers (its LU is needed for y) but stores only
+// y_l, and the back substitution reads the kept E_l.  That moves 18 values
+// per prism slot fewer than storing E with every solve.  Scratch values go
+// as 16-byte pairs.  The arithmetic type C is double (the FP64 and
+// FP32-state/FP64-solve forms) or float (the FP32-everywhere form); the
+// scratch then holds values of type C.
 #include "internal.h"
 
 namespace sdg {
@@ -107,6 +115,8 @@ __device__ __forceinline__ C penalty(C eta, C ka, C kb, C ha, C hb) {
   return eta * (C)0.5 * (ka + kb) / (ha < hb ? ha : hb);
 }
 
+// NF = 0: the factor sweep (store E_l only, no back substitution);
+// NF > 0: the solve (store y_l only, back substitution with the kept E_l).
 template <typename S, typename C, int NF>
 __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const DevMesh& m = a.m;
@@ -124,15 +134,17 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const double* __restrict__ kap = a.kappa;
   const S* __restrict__ Tst = static_cast<const S*>(a.Tstar);
   S* __restrict__ Tout = static_cast<S*>(a.Tout);
-  CPair<C>* __restrict__ Psc = reinterpret_cast<CPair<C>*>(a.scratch);
-  constexpr int kNV = 18 + 6 * NF;   // values per slot (even)
+  CPair<C>* __restrict__ Psc = reinterpret_cast<CPair<C>*>(a.scratch);   // E_l: pairs 0..8
+  CPair<C>* __restrict__ Ysc = Psc + 9 * SL;                              // y_l: pairs 9..9+3NF-1
+  constexpr int kNY = 6 * NF;        // y values per slot (even)
   const C sd = Jh * (C)(1.0 / 12.0), so = Jh * (C)(1.0 / 24.0);   // M_h diagonal / off-diagonal
 
   // ---------------- forward sweep ----------------
   // A layer's stage values and the next layer's level heights are loaded
   // one layer ahead (at clamped, always valid slots), before this layer's
   // scratch stores, so their latency is covered by this layer's arithmetic.
-  auto load_t = [&](int l, C (&t)[NF][6]) {
+  constexpr int kF = NF > 0 ? NF : 1;   // array extent (the factor sweep has no fields)
+  auto load_t = [&](int l, C (&t)[kF][6]) {
     const size_t p = p0 + (size_t)l * kCell;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -142,11 +154,11 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   LayerGeo<C> gc, gn, gpre;
   load_layer(m, lt0, gc);
   load_layer(m, lt0 + (size_t)(N > 1 ? 1 : 0) * kCell, gpre);
-  C tpre[NF][6];
-  load_t(0, tpre);
+  C tpre[kF][6];
+  if (NF > 0) load_t(0, tpre);
   C kvp[6], kvc[6];        // Kv of layers l-1 and l
   C Ep[6][3];              // E_{l-1}
-  C yp[NF][6];             // y_{l-1}
+  C yp[kF][6];             // y_{l-1}
   C kp = (C)0.0, hp = (C)0.0;    // kappa, hbar of layer l-1
   vertical_stiffness(gc, Jh, kvc);
 
@@ -154,13 +166,13 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     const size_t p = p0 + (size_t)l * kCell;
     const C kc = (C)kap[l];
     const bool below = l < N - 1;
-    C t[NF][6];
+    C t[kF][6];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
       for (int i = 0; i < 6; ++i) t[f][i] = tpre[f][i];
     gn = gpre;
-    load_t(l + 1 < N ? l + 1 : N - 1, tpre);
+    if (NF > 0) load_t(l + 1 < N ? l + 1 : N - 1, tpre);
     load_layer(m, lt0 + (size_t)(l + 2 < N ? l + 2 : N - 1) * kCell, gpre);
     const C kn = below ? (C)kap[l + 1] : (C)0.0;
     C mz[6];
@@ -202,7 +214,7 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     }
 
     // right-hand sides r = M T*
-    C r[NF][6];
+    C r[kF][6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
 #pragma unroll
@@ -327,21 +339,22 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) yp[f][i] = z[i];
     }
-    {
-      C sv[kNV];
 #pragma unroll
-      for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 6; ++i)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          Ep[i][q] = Ec[i][q];
-          sv[i * 3 + q] = Ec[i][q];
-        }
+      for (int q = 0; q < 3; ++q) Ep[i][q] = Ec[i][q];
+    if (NF == 0) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        Psc[(size_t)k * SL + p] = CPair<C>{Ec[(2 * k) / 3][(2 * k) % 3], Ec[(2 * k + 1) / 3][(2 * k + 1) % 3]};
+    } else {
+      C sv[kNY > 0 ? kNY : 2];
 #pragma unroll
       for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int i = 0; i < 6; ++i) sv[18 + f * 6 + i] = yp[f][i];
+        for (int i = 0; i < 6; ++i) sv[f * 6 + i] = yp[f][i];
 #pragma unroll
-      for (int k = 0; k < kNV / 2; ++k) Psc[(size_t)k * SL + p] = CPair<C>{sv[2 * k], sv[2 * k + 1]};
+      for (int k = 0; k < kNY / 2; ++k) Ysc[(size_t)k * SL + p] = CPair<C>{sv[2 * k], sv[2 * k + 1]};
     }
     // advance the carried layer quantities
 #pragma unroll
@@ -354,9 +367,11 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
     }
   }
 
+  if (NF == 0) return;
+
   // ---------------- back substitution ----------------
   // x_{N-1} = y_{N-1} (still in yp)
-  C xn[NF][6];
+  C xn[kF][6];
   {
     const size_t p = p0 + (size_t)(N - 1) * kCell;
 #pragma unroll
@@ -369,13 +384,20 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   }
   // kvp, kp, hp describe layer N-1 now.  E_l, y_l and the layer's levels
   // are loaded one layer ahead.
+  constexpr int kNV = 18 + kNY;
   auto load_sv = [&](int l, C (&sv)[kNV], LayerGeo<C>& g) {
     const size_t p = p0 + (size_t)l * kCell;
 #pragma unroll
-    for (int k = 0; k < kNV / 2; ++k) {
+    for (int k = 0; k < 9; ++k) {
       const CPair<C> v = Psc[(size_t)k * SL + p];
       sv[2 * k] = v.lo;
       sv[2 * k + 1] = v.hi;
+    }
+#pragma unroll
+    for (int k = 0; k < kNY / 2; ++k) {
+      const CPair<C> v = Ysc[(size_t)k * SL + p];
+      sv[18 + 2 * k] = v.lo;
+      sv[18 + 2 * k + 1] = v.hi;
     }
     load_layer(m, lt0 + (size_t)l * kCell, g);
   };
@@ -432,8 +454,12 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
 }
 
 template <typename S, typename C>
-hipError_t launch_s(const SolveArgs& a, hipStream_t s) {
+hipError_t launch_s(const SolveArgs& a, bool factor, hipStream_t s) {
   dim3 grid(a.m.n_cells), block(kCell);
+  if (factor) {
+    hipLaunchKernelGGL((vsolve_kernel<S, C, 0>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   switch (a.n_fields) {
     case 1: hipLaunchKernelGGL((vsolve_kernel<S, C, 1>), grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL((vsolve_kernel<S, C, 2>), grid, block, 0, s, a); break;
@@ -446,10 +472,10 @@ hipError_t launch_s(const SolveArgs& a, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, hipStream_t s) {
+hipError_t launch_vsolve(const SolveArgs& a, bool fp32_state, bool fp32_solve, bool factor, hipStream_t s) {
   if (a.m.n_cells == 0) return hipSuccess;
-  if (!fp32_state) return launch_s<double, double>(a, s);
-  return fp32_solve ? launch_s<float, float>(a, s) : launch_s<float, double>(a, s);
+  if (!fp32_state) return launch_s<double, double>(a, factor, s);
+  return fp32_solve ? launch_s<float, float>(a, factor, s) : launch_s<float, double>(a, factor, s);
 }
 
 }  // namespace sdg
