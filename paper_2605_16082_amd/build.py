@@ -1,6 +1,9 @@
 """Build libslimdg.so (HIP, gfx950) in the package directory.
 
-    python -m paper_2605_16082_amd.build
+    python -m paper_2605_16082_amd.build [--sanitize]
+
+--sanitize builds _build/asan/libslimdg_asan.so instead, with the host code
+under AddressSanitizer and UndefinedBehaviorSanitizer (device code as usual).
 
 Every HIP source is compiled with hipcc for gfx950 only, with packed FP32
 instructions disabled, then linked into one shared library next to this file.
@@ -50,16 +53,40 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build (device code
+# unchanged): every -fsanitize applies to the host pass only.
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+ASAN_LIB = os.path.join(BUILD, "asan", "libslimdg_asan.so")
+
+
+def asan_runtime() -> str:
+    """The clang AddressSanitizer runtime (it also carries the UBSan
+    handlers), to LD_PRELOAD into the Python process that loads ASAN_LIB."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(_hipcc())), "..", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    path = _run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"]).stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("AddressSanitizer runtime not found")
+    return path
+
+
+def build_sanitized(verbose: bool = False, jobs: int = 8) -> str:
+    """Compile the library with host-side ASan/UBSan into _build/asan."""
+    return build(verbose, jobs, extra=SANITIZE_FLAGS, out=ASAN_LIB, objdir=os.path.join(BUILD, "asan"))
+
+
+def build(verbose: bool = False, jobs: int = 8, extra=(), out: str = LIB, objdir: str = BUILD) -> str:
     """Compile every csrc/*.hip for gfx950 and link libslimdg.so; returns its path."""
     hipcc = _hipcc()
-    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(objdir, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in srcs]
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
 
     def compile_one(pair):
         src, obj = pair
-        cmd = [hipcc, *HIPFLAGS, "-c", src, "-o", obj]
+        cmd = [hipcc, *HIPFLAGS, *extra, "-c", src, "-o", obj]
         r = _run(cmd)
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -69,13 +96,16 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
         list(ex.map(compile_one, zip(srcs, objs)))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp])
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB, flush=True)
-    return LIB
+        print("built", out, flush=True)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose="-v" in sys.argv)
+    else:
+        build(verbose="-v" in sys.argv)

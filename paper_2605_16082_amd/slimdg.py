@@ -15,12 +15,15 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libslimdg.so")
+# SLIMDG_LIB selects another build of the same library (the host-sanitizer
+# build of the ABI tests); by default the in-tree libslimdg.so.
+LIB_PATH = os.environ.get("SLIMDG_LIB") or os.path.join(_PKG, "libslimdg.so")
 
 SDG_FP64, SDG_FP32, SDG_FP32_STATE_FP64_SOLVE = 0, 1, 2
 SDG_DV_VU, SDG_DV_VD = 0, 1
 SDG_SCHEME_SSPRK3_LIE, SDG_SCHEME_SPLIT_IMEX = 0, 1
 SDG_DV_MAX_COMP = 4
+SDG_PROBE_READ, SDG_PROBE_WRITE, SDG_PROBE_COPY = 0, 1, 2
 STATUS_NAMES = {0: "SDG_OK", -1: "SDG_E_ARG", -2: "SDG_E_MESH", -3: "SDG_E_HIP", -4: "SDG_E_STATE",
                 -5: "SDG_E_UNSUPPORTED", -6: "SDG_E_NUMERIC", -7: "SDG_E_WORKSPACE"}
 
@@ -30,7 +33,7 @@ EXPORTED = (
     "sdg_set_fields", "sdg_rhs_3d", "sdg_rk_stage", "sdg_vertical_implicit_solve", "sdg_step",
     "sdg_mass", "sdg_sync", "sdg_get_tuning", "sdg_set_tuning", "sdg_autotune",
     "sdg_graph_capture_step", "sdg_graph_launch", "sdg_apply_mass", "sdg_m_dot", "sdg_step_adjoint",
-    "sdg_column_dv_solve", "sdg_step_adjoint_imex", "sdg_mass_noalloc",
+    "sdg_column_dv_solve", "sdg_step_adjoint_imex", "sdg_mass_noalloc", "sdg_stream_probe",
 )
 
 
@@ -129,6 +132,7 @@ def load_library(path: str | None = None):
         "sdg_column_dv_solve": ([vp, i32, i32, vp, vp], i32),
         "sdg_step_adjoint_imex": ([vp, vp, vp, vp, vp], i32),
         "sdg_mass_noalloc": ([vp, vp, vp], i32),
+        "sdg_stream_probe": ([i32, vp, vp, sz, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -396,6 +400,17 @@ class SlimDG:
         self._check_nodal(out, n_comp)
         _check(self.lib.sdg_column_dv_solve(self.ctx, int(kind), n_comp, _ptr(F), _ptr(out)))
         return out
+
+
+def stream_probe(kind: int, src, dst, nbytes: int, workgroups: int):
+    """Enqueue one streaming probe (SDG_PROBE_READ / _WRITE / _COPY) on torch's
+    current stream; src and dst are device tensors (src may be None for WRITE)."""
+    import torch
+
+    lib = load_library()
+    stream = torch.cuda.current_stream(dst.device)
+    _check(lib.sdg_stream_probe(int(kind), None if src is None else _ptr(src), _ptr(dst), int(nbytes),
+                                int(workgroups), ctypes.c_void_p(stream.cuda_stream)))
 
 
 def from_workload(w, precision: int = SDG_FP64, device: int = 0, time_scheme: int = SDG_SCHEME_SSPRK3_LIE,
