@@ -136,15 +136,41 @@ def run_gpu(w, precision, steps, warmup, torch, P_mod):
 
 
 def copy_bandwidth(torch, n_bytes=1 << 30, reps=5):
-    """Read + write GB/s of a device-to-device copy of n_bytes (torch's copy
-    kernel): the practical streaming ceiling the roofline is also quoted
-    against."""
+    """Read + write GB/s of a device-to-device copy of n_bytes by torch's own
+    copy kernel (context only: the library's probes below reach more)."""
     src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     t = time_calls(torch, lambda: dst.copy_(src), reps)
     del src, dst
     torch.cuda.empty_cache()
     return 2 * n_bytes / t / 1e9
+
+
+def stream_ceiling(torch, P_mod, n_bytes=1 << 31, reps=10):
+    """The library's streaming probes (16-byte accesses per lane, HIP events
+    on the launch stream): read-only, write-only and copy GB/s (copy counts
+    read + write bytes), each the best over grid sizes of 1-32 workgroups per
+    CU.  The largest is the measured streaming ceiling."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    src = torch.ones(n_bytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    out = {"bytes": n_bytes}
+    for name, kind, mult in (("read", P_mod.SDG_PROBE_READ, 1), ("write", P_mod.SDG_PROBE_WRITE, 1),
+                             ("copy", P_mod.SDG_PROBE_COPY, 2)):
+        best, best_wg = 0.0, 0
+        for per_cu in (1, 2, 4, 8, 16, 32):
+            wg = per_cu * n_cu
+            s_ = None if kind == P_mod.SDG_PROBE_WRITE else src
+            t = time_calls(torch, lambda: P_mod.stream_probe(kind, s_, dst, n_bytes, wg), reps)
+            gbs = mult * n_bytes / t / 1e9
+            if gbs > best:
+                best, best_wg = gbs, wg
+        out[f"{name}_GBps"] = best
+        out[f"{name}_workgroups"] = best_wg
+    out["ceiling_GBps"] = max(out["read_GBps"], out["write_GBps"], out["copy_GBps"])
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def event_time(torch, fn):
@@ -384,6 +410,17 @@ def adjoint_form(torch, P_mod, W, n_steps=200, every=20):
     return out
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(w, budget_s=20.0):
     """The FP64 oracle, single-threaded BLAS, on a bounded sample: RK stages
     on a block of prisms and column solves on a block of columns; scaled to
@@ -407,6 +444,13 @@ def cpu_baseline(w, budget_s=20.0):
     t0 = time.perf_counter()
     O.implicit_solve(m, w.kappa, w.dt, w.T0, w.penalty, columns=np.arange(n_col))
     t_solve = (time.perf_counter() - t0) / (n_col * int(w.nlayers[0]))   # s per prism
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"library": d.get("internal_api"), "num_threads": d.get("num_threads")}
+                for d in threadpool_info() if d.get("user_api") == "blas"]
+    except Exception:  # pragma: no cover
+        pass
     if limiter is not None:
         limiter.unregister()
     per_prism_step = 3 * t_stage + t_solve
@@ -421,6 +465,9 @@ def cpu_baseline(w, budget_s=20.0):
         "stage_rate": 6 * F / t_stage,
         "s_per_prism_stage": t_stage,
         "s_per_prism_solve": t_solve,
+        "cpu_model": cpu_model(),
+        "logical_cpus": os.cpu_count(),
+        "blas_during_timing": blas,
     }
 
 
@@ -472,7 +519,9 @@ def main():
         print(json.dumps({"hdiff_form": hdiff_form(w, 10, torch, P_mod)}), flush=True)
         return
     copy_gbps = copy_bandwidth(torch)
-    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
+    log(f"torch device copy: {copy_gbps:.0f} GB/s (read + write)")
+    probe = stream_ceiling(torch, P_mod)
+    log("stream probes", json.dumps(probe))
     r64 = run_gpu(w, P_mod.SDG_FP64, args.steps, args.warmup, torch, P_mod)
     log("fp64", json.dumps(r64))
     r32 = None
@@ -496,6 +545,8 @@ def main():
         cpu = cpu_baseline(w)
         log("cpu", json.dumps(cpu))
 
+    traffic = measured_traffic(r64["tuning"])
+    alg_mean = sum(r64["stage_bytes_per_launch"]) / 3
     out = {
         "metric": METRIC,
         "value": r64["value"],
@@ -524,11 +575,16 @@ def main():
             "peak": HBM_PEAK / 1e9,
             "unit": "GB/s",
             "frac": r64["stage_GBps"] * 1e9 / HBM_PEAK,
-            "copy_GBps": copy_gbps,
-            "frac_of_copy": r64["stage_GBps"] / copy_gbps,
-            "traffic": measured_traffic(r64["tuning"]),
+            "stream_probe": probe,
+            "frac_of_stream_ceiling": r64["stage_GBps"] / probe["ceiling_GBps"],
+            "torch_copy_GBps": copy_gbps,
+            "traffic": traffic,
             "traffic_unit": "bytes per launch (mean of the 3 stage launches)",
-            "algorithmic_bytes_mean_per_launch": sum(r64["stage_bytes_per_launch"]) / 3,
+            "traffic_range": None if traffic is None else [alg_mean, traffic],
+            "traffic_note": "FETCH_SIZE + WRITE_SIZE scaled by a 1 GiB copy; FETCH_SIZE counts L2 misses, "
+                            "Infinity-Cache hits included, so the figure bounds HBM bytes from above and the "
+                            "algorithmic bytes bound them from below",
+            "algorithmic_bytes_mean_per_launch": alg_mean,
         },
         "kernels_fp64": {
             "t_stage_s": r64["t_stage"], "t_solve_s": r64["t_solve"],

@@ -365,6 +365,21 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
 /* Wait for the context's stream and report any asynchronous HIP error. */
 sdg_status sdg_sync(sdg_ctx* ctx);
 
+/* Measurement aid, not part of the method: the device's streaming bandwidth
+ * with 16-byte accesses per lane, the ceiling against which the kernels'
+ * algorithmic bandwidth is read besides the HBM peak.
+ *   SDG_PROBE_READ:  sums dev_src (bytes), one double per workgroup to dev_dst;
+ *   SDG_PROBE_WRITE: fills dev_dst (bytes) with 1.0;
+ *   SDG_PROBE_COPY:  copies dev_src to dev_dst (bytes each).
+ * Device pointers owned by the caller, 16-byte aligned; bytes a positive
+ * multiple of 16; workgroups (256 threads each) >= 1 (for READ, dev_dst holds
+ * at least that many doubles).  Enqueued on hip_stream (NULL: the default
+ * stream), no synchronisation, no context needed; SDG_E_ARG on a bad
+ * argument, SDG_E_HIP if the launch fails. */
+typedef enum { SDG_PROBE_READ = 0, SDG_PROBE_WRITE = 1, SDG_PROBE_COPY = 2 } sdg_probe_kind;
+sdg_status sdg_stream_probe(int kind, const void* dev_src, void* dev_dst, size_t bytes, int workgroups,
+                            void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

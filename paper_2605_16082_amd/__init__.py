@@ -11,6 +11,9 @@ from .slimdg import (  # noqa: F401
     SDG_FP32,
     SDG_FP32_STATE_FP64_SOLVE,
     SDG_FP64,
+    SDG_PROBE_COPY,
+    SDG_PROBE_READ,
+    SDG_PROBE_WRITE,
     SDG_SCHEME_SPLIT_IMEX,
     SDG_SCHEME_SSPRK3_LIE,
     EXPORTED,
@@ -21,6 +24,7 @@ from .slimdg import (  # noqa: F401
     Tuning,
     from_workload,
     load_library,
+    stream_probe,
 )
 from .autograd import (  # noqa: F401
     MNorm,
