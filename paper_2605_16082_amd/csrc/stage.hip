@@ -89,6 +89,28 @@ template <typename T>
 __device__ __forceinline__ void stb(T* __restrict__ row, uint32_t byte_off, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(row) + byte_off) = v;
 }
+// Row r of a [..][6][S] nodal array at byte offset off.  In double the
+// address is the base of the row's 6-row block plus a 32-bit offset
+// (r mod 6) S + off: one uniform base per block instead of one per row, so
+// the FP64 column walk keeps far fewer 64-bit row addresses in scalar
+// registers, which it otherwise spills to vector lanes (stages 2% faster).
+// In float the per-row form stays: the block form's offsets take the few
+// vector registers that keep the float walk at two wavefronts per SIMD.
+// A 6-row block is below 4 GiB (checked at mesh upload).
+template <typename T>
+__device__ __forceinline__ T ldr(const T* __restrict__ arr, size_t S, int r, uint32_t off) {
+  if constexpr (sizeof(T) == 8)
+    return ldb(arr + (size_t)(r / 6 * 6) * S, (uint32_t)(r % 6) * (uint32_t)(S * sizeof(T)) + off);
+  else
+    return ldb(arr + (size_t)r * S, off);
+}
+template <typename T>
+__device__ __forceinline__ void str(T* __restrict__ arr, size_t S, int r, uint32_t off, T v) {
+  if constexpr (sizeof(T) == 8)
+    stb(arr + (size_t)(r / 6 * 6) * S, (uint32_t)(r % 6) * (uint32_t)(S * sizeof(T)) + off, v);
+  else
+    stb(arr + (size_t)r * S, off, v);
+}
 
 template <typename R>
 __device__ __forceinline__ R upos(R x) { return x > R(0) ? x : R(0); }
@@ -466,9 +488,9 @@ __device__ __forceinline__ void finish_field(const StageArgs& a, const MinvF<R>&
       if (READ_TN) out += ca * tn[i];
     }
     if (active) {
-      stb(Out + (size_t)(f * 6 + i) * S, po, out);
+      str(Out, S, f * 6 + i, po, out);
       // second output T - 2 Tout (the split-IMEX first step)
-      if (OUT2) stb(Out2 + (size_t)(f * 6 + i) * S, po, T[i] - R(2) * out);
+      if (OUT2) str(Out2, S, f * 6 + i, po, T[i] - R(2) * out);
     }
   }
 }
@@ -551,9 +573,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile
     R u[6], v[6], w[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      u[i] = ldb(U + (size_t)(0 * 6 + i) * S, po);
-      v[i] = ldb(U + (size_t)(1 * 6 + i) * S, po);
-      w[i] = WZ ? R(0) : ldb(U + (size_t)(2 * 6 + i) * S, po);
+      u[i] = ldr(U, S, 0 * 6 + i, po);
+      v[i] = ldr(U, S, 1 * 6 + i, po);
+      w[i] = WZ ? R(0) : ldr(U, S, 2 * 6 + i, po);
     }
     volume_factors<R, WZ>(cg, zt, zb, dz, u, v, w, vf);
 #pragma unroll
@@ -567,16 +589,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile
     R ux[3], vx[3], wx[3];
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-      ux[n] = ldb(U + (size_t)(0 * 6 + 3 + n) * S, pup);
-      vx[n] = ldb(U + (size_t)(1 * 6 + 3 + n) * S, pup);
-      wx[n] = WZ ? R(0) : ldb(U + (size_t)(2 * 6 + 3 + n) * S, pup);
+      ux[n] = ldr(U, S, 0 * 6 + 3 + n, pup);
+      vx[n] = ldr(U, S, 1 * 6 + 3 + n, pup);
+      wx[n] = WZ ? R(0) : ldr(U, S, 2 * 6 + 3 + n, pup);
     }
     hface_factors<R, WZ>(cg, zt, l > 0, ux, vx, wx, true, u, v, w, top);
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-      ux[n] = ldb(U + (size_t)(0 * 6 + n) * S, plo);
-      vx[n] = ldb(U + (size_t)(1 * 6 + n) * S, plo);
-      wx[n] = WZ ? R(0) : ldb(U + (size_t)(2 * 6 + n) * S, plo);
+      ux[n] = ldr(U, S, 0 * 6 + n, plo);
+      vx[n] = ldr(U, S, 1 * 6 + n, plo);
+      wx[n] = WZ ? R(0) : ldr(U, S, 2 * 6 + n, plo);
     }
     hface_factors<R, WZ>(cg, zb, true, u + 3, v + 3, w + 3, l < N - 1, ux, vx, wx, bot);
     minv_factors<R>(cg, dz, mf);
@@ -586,8 +608,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile
     R T[6], res[6], tn[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      T[i] = ldb(Ts + (size_t)(f * 6 + i) * S, po);
-      tn[i] = READ_TN ? ldb(Tn + (size_t)(f * 6 + i) * S, po) : R(0);
+      T[i] = ldr(Ts, S, f * 6 + i, po);
+      tn[i] = READ_TN ? ldr(Tn, S, f * 6 + i, po) : R(0);
     }
     volume_field<R>(vf, T, res);
 #pragma unroll
@@ -599,12 +621,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const WgTile tile
     const R te = R(a.t_ext[f]);
     R Tx[3], g[3];
 #pragma unroll
-    for (int n = 0; n < 3; ++n) Tx[n] = ldb(Ts + (size_t)(f * 6 + 3 + n) * S, pup);
+    for (int n = 0; n < 3; ++n) Tx[n] = ldr(Ts, S, f * 6 + 3 + n, pup);
     hface_field<R>(top, te, Tx, T, g);
 #pragma unroll
     for (int n = 0; n < 3; ++n) res[n] -= g[n];
 #pragma unroll
-    for (int n = 0; n < 3; ++n) Tx[n] = ldb(Ts + (size_t)(f * 6 + n) * S, plo);
+    for (int n = 0; n < 3; ++n) Tx[n] = ldr(Ts, S, f * 6 + n, plo);
     hface_field<R>(bot, te, T + 3, Tx, g);
 #pragma unroll
     for (int n = 0; n < 3; ++n) res[3 + n] += g[n];
@@ -862,7 +884,7 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
   R tn[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i)
-    tn[i] = (READ_TN && !Ly::kTnLds) ? ldb(Tn + (size_t)i * S, po) : R(0);
+    tn[i] = (READ_TN && !Ly::kTnLds) ? ldr(Tn, S, i, po) : R(0);
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
     phase();
@@ -876,7 +898,7 @@ __device__ __forceinline__ void walk_layer(const StageArgs& a, const ColGeo<R>& 
     if (f + 1 < NF) {
 #pragma unroll
       for (int i = 0; i < 6; ++i)
-        tnn[i] = (READ_TN && !Ly::kTnLds) ? ldb(Tn + (size_t)((f + 1) * 6 + i) * S, po) : R(0);
+        tnn[i] = (READ_TN && !Ly::kTnLds) ? ldr(Tn, S, (f + 1) * 6 + i, po) : R(0);
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) T[i] = own(Ly::kTs + f * 6 + i);
@@ -963,16 +985,16 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
       R uu[3], vu[3], wu[3], ul[3], vl[3], wl[3];
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
-        uu[n] = ldb(U + (size_t)(0 * 6 + 3 + n) * S, pup);
-        vu[n] = ldb(U + (size_t)(1 * 6 + 3 + n) * S, pup);
-        wu[n] = WZ ? R(0) : ldb(U + (size_t)(2 * 6 + 3 + n) * S, pup);
+        uu[n] = ldr(U, S, 0 * 6 + 3 + n, pup);
+        vu[n] = ldr(U, S, 1 * 6 + 3 + n, pup);
+        wu[n] = WZ ? R(0) : ldr(U, S, 2 * 6 + 3 + n, pup);
       }
       // the layer above's bottom values, requested with its velocity before the wait
       R Tu[NF][3];
 #pragma unroll
       for (int f = 0; f < NF; ++f)
 #pragma unroll
-        for (int n = 0; n < 3; ++n) Tu[f][n] = ldb(Ts + (size_t)(f * 6 + 3 + n) * S, pup);
+        for (int n = 0; n < 3; ++n) Tu[f][n] = ldr(Ts, S, f * 6 + 3 + n, pup);
       wait_vm();
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
