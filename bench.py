@@ -81,6 +81,16 @@ def solve_bytes(P, C, n_lev, F, es):
     return (12 * F * P + 3 * n_lev) * es + C * 8
 
 
+def tuning_dict(s, tuning):
+    """The chosen launch shape; tile_layers 0 = walks segmented per depth
+    bucket, listed in walk_layers (buckets 1-8, 9-16, 17-24, 25-32, 33-48,
+    > 48 layers; negative = balanced segments)."""
+    d = dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))
+    if d["tile_layers"] == 0:
+        d["walk_layers"] = s.walk_layers()
+    return d
+
+
 def time_calls(torch, fn, reps):
     """Average duration of fn() over reps calls, HIP events on the current stream."""
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -128,7 +138,7 @@ def run_gpu(w, precision, steps, warmup, torch, P_mod):
         "stage_bytes_per_launch": [int(b) for b in by],
         "solve_GBps": sb / t_sv / 1e9,
         "solve_bytes_per_launch": int(sb),
-        "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning)),
+        "tuning": tuning_dict(s, tuning),
     }
     del s, U, kappa, state, A, B
     torch.cuda.empty_cache()
@@ -279,7 +289,7 @@ def split_imex_form(w, steps, torch, P_mod):
         s.set_fields(x.copy_(s.scatter(w.T0)))
         t = event_time(torch, lambda: s.step(steps)) / steps
         r = {"ms_per_step": t * 1e3, "dof_steps_per_s": 6 * P * F / t,
-             "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))}
+             "tuning": tuning_dict(s, tuning)}
         if key == "imex_fp64":
             r["max_rel_diff_per_field_vs_lie_fp64"] = field_errors(torch, x, keep["lie_fp64"])
             r["speedup_vs_lie_fp64"] = out["lie_fp64"]["ms_per_step"] / r["ms_per_step"]
@@ -318,7 +328,7 @@ def hdiff_form(w, steps, torch, P_mod, reps=10):
     res = {"ms_per_step_with": t_on * 1e3, "ms_per_step_without": t_off * 1e3,
            "hdiff_kernel_ms": t_k * 1e3, "hdiff_bytes_per_launch": int(by),
            "hdiff_GBps": by / t_k / 1e9, "hdiff_frac": by / t_k / HBM_PEAK,
-           "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))}
+           "tuning": tuning_dict(s, tuning)}
     del s, U, kappa, x, out_buf
     torch.cuda.empty_cache()
     return res
@@ -345,7 +355,7 @@ def batched_form(torch, P_mod, W, steps, warmup):
         s.graph_launch(warmup)
         t = event_time(torch, lambda: s.graph_launch(steps)) / steps
         r = {"ms_per_step": t * 1e3, "value": 18 * P * F / t,
-             "tuning": dict(zip(("tile_layers", "xcd_remap", "persistent"), tuning))}
+             "tuning": tuning_dict(s, tuning)}
         m = s.mass(x)
         if ref is None:
             ref, m_ref, vol = x, m, unit_mass(s)
@@ -569,7 +579,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": ("walk_kernel (column walk" if r64["tuning"]["tile_layers"] >= 8 else "stage_kernel (one thread per prism")
+            "kernel": ("walk_kernel (column walk" if r64["tuning"]["tile_layers"] in (0, 8, 12, 16, 32)
+                       else "stage_kernel (one thread per prism")
                       + ", fused rhs + SSP-RK3 stage), mean of the 3 stage launches",
             "achieved": r64["stage_GBps"],
             "peak": HBM_PEAK / 1e9,

@@ -78,7 +78,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 6
+#define SDG_ABI_VERSION 7
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -261,31 +261,46 @@ sdg_status sdg_mass(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 sdg_status sdg_mass_noalloc(sdg_ctx* ctx, const void* dev_T, double* host_mass);
 
 /* Launch shape of the fused stage kernel (the paper's section 4.1 shows
- * throughput depending on the column block shape; here the library measures
- * it).  Results do not depend on it (bitwise).
+ * throughput depending on the column block shape; section 2.1.2 sizes a
+ * cell's block by its deepest column; here the library measures it).
+ * Results do not depend on it (bitwise).
  * tile_layers: 1, 2 or 4 = layers per workgroup of 64 columns, one thread per
  *   prism (default 2); 8, 12, 16 or 32 = one wavefront walks that many layers of
  *   a cell, prefetching the next layer into LDS while computing the current;
+ *   0 = a column walk whose segmentation depends on the cell's depth D, by
+ *   bucket b = 0..5 for D in 1-8, 9-16, 17-24, 25-32, 33-48, > 48:
+ *   walk_layers[b] = L in 8..64 cuts the cell into walks of L layers (the last
+ *   one shorter), L in -64..-8 into ceil(D / |L|) walks of balanced lengths
+ *   (e.g. D = 30, L = -12: 10 + 10 + 10);
  * xcd_remap: 1 = give each XCD one contiguous range of tiles (default);
  * persistent: 1 = launch only as many workgroups as the device holds at once,
  *   each walking tiles with a stride (default 0: one workgroup per tile).
+ * walk_layers is read only with tile_layers = 0 and reported as zeros
+ * otherwise; setting it needs an uploaded mesh (the table is built for it and
+ * synchronises the stream), and a mesh upload returns to 2-layer tiles.
  * The adjoint stages use tile_layers and xcd_remap of a one-thread shape;
  * under a walk shape they use 2-layer tiles with the XCD remap.  They ignore
  * persistent. */
+#define SDG_DEPTH_BUCKETS 6
 typedef struct {
   int32_t tile_layers;
   int32_t xcd_remap;
   int32_t persistent;
+  int32_t walk_layers[SDG_DEPTH_BUCKETS];
 } sdg_tuning;
 
 sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out);
 sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* tuning);
 
-/* Time every stage-kernel launch shape (6 tile heights x XCD remap off/on x
+/* Time every stage-kernel launch shape (7 tile heights x XCD remap off/on x
  * persistent off/on), each over reps repetitions of the three stages of a
  * step on the set fields and velocity (the fields are only read; the stages
- * write the workspace stage buffers), and keep the fastest.  Synchronises
- * the stream.  `chosen` may be NULL. */
+ * write the workspace stage buffers), and keep the fastest.  When a column
+ * walk wins, also choose a segmentation per depth bucket (walk_layers, fixed
+ * 8/12/16/32/64 or balanced 8/12/16/24/32), timing each bucket's tiles alone
+ * with that walk's XCD remap and persistent setting, and keep the per-bucket
+ * table (tile_layers = 0) if all of it is faster than the uniform walk.
+ * Synchronises the stream.  `chosen` may be NULL. */
 sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen);
 
 /* Capture one sdg_step (three stages and the column solve, on the set fields)

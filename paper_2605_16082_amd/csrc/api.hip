@@ -49,7 +49,7 @@ struct Plan {
   int n_tiles[kTileChoices] = {};
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
-      o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_stage_a, o_stage_b, o_scratch,
+      o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_tiles_bucket, o_stage_a, o_stage_b, o_scratch,
       o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, total;
   size_t state_bytes, velocity_bytes;
 };
@@ -186,6 +186,8 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_zl = take(sizeof(double) * 3 * (size_t)P.n_lslots);
   P.o_zl32 = take(sizeof(float) * 3 * (size_t)P.n_lslots);
   for (int t = 0; t < kTileChoices; ++t) P.o_tiles[t] = take(sizeof(WgTile) * std::max(P.n_tiles[t], 1));
+  // per-bucket walks are at least 8 layers long: no more tiles than the 8-layer table
+  P.o_tiles_bucket = take(sizeof(WgTile) * std::max(P.n_tiles[3], 1));
   P.o_stage_a = take(P.state_bytes);
   P.o_stage_b = take(P.state_bytes);
   P.o_scratch = take(sizeof(double) * (size_t)(18 + 6 * P.F) * (size_t)P.n_slots);
@@ -256,6 +258,9 @@ struct sdg_ctx {
   DevMesh dm{};
   char* ws = nullptr;
   WgTile* tiles[kTileChoices] = {};
+  WgTile* tiles_bucket = nullptr;     // per-depth-bucket walk table (tile_choice == kBucketChoice)
+  int n_tiles_bucket = 0;
+  int walk_layers[kDepthBuckets] = {};
   // launch shape of the stage kernel (chosen by sdg_set_tuning / sdg_autotune)
   int tile_choice = 1;   // index into kTileLayerOptions (2 layers)
   int xcd = 1;
@@ -408,16 +413,16 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
     const int T = kTileLayerOptions[t];
     tiles[t].reserve(P.n_tiles[t]);
     for (int k = 0; k < P.n_cells; ++k)
-      for (int l0 = 0; l0 < P.cell_depth[k]; l0 += T) tiles[t].push_back({k, l0});
+      for (int l0 = 0; l0 < P.cell_depth[k]; l0 += T)
+        tiles[t].push_back({k, (uint16_t)l0, (uint16_t)std::min(T, P.cell_depth[k] - l0)});
     // Full tiles first, shorter ones (a cell's last segment) after them, each
     // group in cell order.  A persistent grid strides through the table with
     // a stride that is a multiple of 8; in cell order every workgroup would
     // get the same segment of each cell it visits, and those that get the
     // short last segments would idle while the others finish.  The shorter
     // tiles also make up the tail of a one-tile-per-workgroup launch.
-    std::stable_sort(tiles[t].begin(), tiles[t].end(), [&](const WgTile& x, const WgTile& y) {
-      return std::min(T, P.cell_depth[x.cell] - x.layer0) > std::min(T, P.cell_depth[y.cell] - y.layer0);
-    });
+    std::stable_sort(tiles[t].begin(), tiles[t].end(),
+                     [](const WgTile& x, const WgTile& y) { return x.nlay > y.nlay; });
   }
   for (int m = 0; m < P.n_members; ++m)
     for (int c = P.member_off[m]; c < P.member_off[m + 1]; ++c) colmem[c] = m;
@@ -503,6 +508,9 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   const Plan& Q = ctx->plan;
   ctx->ws = ws;
   for (int t = 0; t < kTileChoices; ++t) ctx->tiles[t] = reinterpret_cast<WgTile*>(ws + Q.o_tiles[t]);
+  ctx->tiles_bucket = reinterpret_cast<WgTile*>(ws + Q.o_tiles_bucket);
+  ctx->n_tiles_bucket = 0;
+  if (ctx->tile_choice == kBucketChoice) ctx->tile_choice = 1;   // the table belongs to the old mesh
   ctx->member_off_dev = reinterpret_cast<int32_t*>(ws + Q.o_member_off);
   ctx->colmass = reinterpret_cast<double*>(ws + Q.o_colmass);
   ctx->msum = reinterpret_cast<double*>(ws + Q.o_msum);
@@ -596,9 +604,15 @@ sdg_status check_explicit(sdg_ctx* ctx, const char* who) {
 StageArgs stage_args(sdg_ctx* ctx, const void* Tn, const void* Ts, void* Tout, double a, double b, double dt) {
   StageArgs s{};
   s.m = ctx->dm;
-  s.tiles = ctx->tiles[ctx->tile_choice];
-  s.n_tiles = ctx->plan.n_tiles[ctx->tile_choice];
-  s.tile_layers = kTileLayerOptions[ctx->tile_choice];
+  if (ctx->tile_choice == kBucketChoice) {
+    s.tiles = ctx->tiles_bucket;
+    s.n_tiles = ctx->n_tiles_bucket;
+    s.tile_layers = kBucketWalkMax;
+  } else {
+    s.tiles = ctx->tiles[ctx->tile_choice];
+    s.n_tiles = ctx->plan.n_tiles[ctx->tile_choice];
+    s.tile_layers = kTileLayerOptions[ctx->tile_choice];
+  }
   s.xcd = ctx->xcd;
   s.persistent = ctx->persistent;
   s.n_cu = ctx->n_cu;
@@ -837,11 +851,67 @@ sdg_status sdg_mass_noalloc(sdg_ctx* ctx, const void* dev_T, double* host_mass) 
   return SDG_OK;
 }
 
+namespace {
+// Walk segments of a cell of D layers for the bucket setting L: L > 0 fixed
+// segments of L layers (the last one shorter), L < 0 the same number of
+// segments, ceil(D / |L|), of balanced lengths (the longer ones first).
+void bucket_segments(int D, int L, std::vector<std::pair<int, int>>& seg) {
+  seg.clear();
+  const int A = L < 0 ? -L : L;
+  const int n = (D + A - 1) / A;
+  if (L > 0) {
+    for (int l0 = 0; l0 < D; l0 += A) seg.push_back({l0, std::min(A, D - l0)});
+  } else {
+    const int q = D / n, r = D % n;
+    for (int i = 0, l0 = 0; i < n; ++i) {
+      const int len = q + (i < r ? 1 : 0);
+      seg.push_back({l0, len});
+      l0 += len;
+    }
+  }
+}
+
+bool valid_walk_setting(int L) {
+  const int A = L < 0 ? -L : L;
+  return A >= kWalkMinLayers && A <= kBucketWalkMax;
+}
+
+// Build the per-bucket walk table for walk_layers (only the cells of bucket
+// `only`, if only >= 0) and upload it; the table lists longer tiles first,
+// each length in cell order.  Synchronises the stream.
+sdg_status upload_bucket_table(sdg_ctx* ctx, const int* walk_layers, int only) {
+  const Plan& P = ctx->plan;
+  std::vector<WgTile> t;
+  t.reserve(P.n_tiles[3]);
+  std::vector<std::pair<int, int>> seg;
+  for (int k = 0; k < P.n_cells; ++k) {
+    const int D = P.cell_depth[k];
+    if (D == 0) continue;
+    const int b = depth_bucket(D);
+    if (only >= 0 && b != only) continue;
+    bucket_segments(D, walk_layers[b], seg);
+    for (auto& sg : seg) t.push_back({k, (uint16_t)sg.first, (uint16_t)sg.second});
+  }
+  if ((int)t.size() > std::max(P.n_tiles[3], 1)) return fail(SDG_E_ARG, "per-bucket walk table too large");
+  std::stable_sort(t.begin(), t.end(), [](const WgTile& x, const WgTile& y) { return x.nlay > y.nlay; });
+  if (!t.empty()) {
+    hipError_t e = hipMemcpyAsync(ctx->tiles_bucket, t.data(), sizeof(WgTile) * t.size(), hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "per-bucket walk table upload");
+  }
+  ctx->n_tiles_bucket = (int)t.size();
+  return SDG_OK;
+}
+}  // namespace
+
 sdg_status sdg_get_tuning(sdg_ctx* ctx, sdg_tuning* out) {
   if (!ctx || !out) return fail(SDG_E_ARG, "sdg_get_tuning: NULL argument");
-  out->tile_layers = kTileLayerOptions[ctx->tile_choice];
+  const bool bucket = ctx->tile_choice == kBucketChoice;
+  out->tile_layers = bucket ? 0 : kTileLayerOptions[ctx->tile_choice];
   out->xcd_remap = ctx->xcd;
   out->persistent = ctx->persistent;
+  for (int b = 0; b < kDepthBuckets; ++b) out->walk_layers[b] = bucket ? ctx->walk_layers[b] : 0;
   g_err.clear();
   return SDG_OK;
 }
@@ -851,9 +921,23 @@ sdg_status sdg_set_tuning(sdg_ctx* ctx, const sdg_tuning* t) {
   int choice = -1;
   for (int i = 0; i < kTileChoices; ++i)
     if (kTileLayerOptions[i] == t->tile_layers) choice = i;
-  if (choice < 0) return fail(SDG_E_ARG, "tile_layers must be 1, 2, 4, 8, 12, 16 or 32 (got %d)", t->tile_layers);
+  if (t->tile_layers == 0) choice = kBucketChoice;
+  if (choice < 0)
+    return fail(SDG_E_ARG, "tile_layers must be 0 (per depth bucket), 1, 2, 4, 8, 12, 16 or 32 (got %d)",
+                t->tile_layers);
   if (t->xcd_remap != 0 && t->xcd_remap != 1) return fail(SDG_E_ARG, "xcd_remap must be 0 or 1");
   if (t->persistent != 0 && t->persistent != 1) return fail(SDG_E_ARG, "persistent must be 0 or 1");
+  if (choice == kBucketChoice) {
+    if (!ctx->have_mesh) return fail(SDG_E_STATE, "per-bucket walks need an uploaded mesh");
+    for (int b = 0; b < kDepthBuckets; ++b)
+      if (!valid_walk_setting(t->walk_layers[b]))
+        return fail(SDG_E_ARG, "walk_layers[%d] = %d: need 8..64 (fixed) or -64..-8 (balanced)", b,
+                    t->walk_layers[b]);
+    DeviceGuard g(ctx->device);
+    sdg_status st = upload_bucket_table(ctx, t->walk_layers, -1);
+    if (st != SDG_OK) return st;
+    for (int b = 0; b < kDepthBuckets; ++b) ctx->walk_layers[b] = t->walk_layers[b];
+  }
   ctx->tile_choice = choice;
   ctx->xcd = t->xcd_remap;
   ctx->persistent = t->persistent;
@@ -881,48 +965,87 @@ sdg_status sdg_autotune(sdg_ctx* ctx, int reps, sdg_tuning* chosen) {
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) return hip_fail(e, "sdg_autotune: hipEventCreate");
+  // mean time of the three stages of a step in the current shape, with
+  // sdg_step's buffer pattern (Tn = the fields, stage inputs and outputs in
+  // the two workspace buffers), so the set fields are only read
+  auto time_shape = [&](float* ms) -> sdg_status {
+    sdg_status s2 = timed_stages(ctx);
+    if (s2 != SDG_OK) return s2;
+    hipError_t e2 = hipEventRecord(e0, ctx->stream);
+    for (int r = 0; r < reps && s2 == SDG_OK; ++r) s2 = timed_stages(ctx);
+    if (s2 != SDG_OK) return s2;
+    if (e2 == hipSuccess) e2 = hipEventRecord(e1, ctx->stream);
+    if (e2 == hipSuccess) e2 = hipEventSynchronize(e1);
+    if (e2 == hipSuccess) e2 = hipEventElapsedTime(ms, e0, e1);
+    return e2 == hipSuccess ? SDG_OK : hip_fail(e2, "sdg_autotune: timing");
+  };
   float best = 1e30f;
-  int best_choice = ctx->tile_choice, best_xcd = ctx->xcd, best_pers = ctx->persistent;
+  int best_choice = ctx->tile_choice == kBucketChoice ? 1 : ctx->tile_choice;
+  int best_xcd = ctx->xcd, best_pers = ctx->persistent;
   for (int shape = 0; shape < kTileChoices * 4 && st == SDG_OK; ++shape) {
-    {
-      const int c = shape >> 2, x = shape & 1, pers = (shape >> 1) & 1;
-      ctx->tile_choice = c;
-      ctx->xcd = x;
-      ctx->persistent = pers;
-      // the three stages of a step with sdg_step's buffer pattern (Tn = the
-      // fields, stage inputs and outputs in the two workspace buffers), so
-      // the set fields are only read
-      st = timed_stages(ctx);
-      if (st != SDG_OK) break;
-      e = hipEventRecord(e0, ctx->stream);
-      for (int r = 0; r < reps && st == SDG_OK; ++r) st = timed_stages(ctx);
-      if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = hip_fail(e, "sdg_autotune: timing");
-        break;
-      }
-      if (ms < best) {
-        best = ms;
-        best_choice = c;
-        best_xcd = x;
-        best_pers = pers;
-      }
+    const int c = shape >> 2, x = shape & 1, pers = (shape >> 1) & 1;
+    ctx->tile_choice = c;
+    ctx->xcd = x;
+    ctx->persistent = pers;
+    float ms = 0.f;
+    st = time_shape(&ms);
+    if (st == SDG_OK && ms < best) {
+      best = ms;
+      best_choice = c;
+      best_xcd = x;
+      best_pers = pers;
     }
+  }
+  // With a column walk fastest, choose each depth bucket's segmentation
+  // (fixed or balanced lengths) by timing that bucket's tiles alone, one
+  // bucket at a time, then keep the per-bucket table if the whole of it
+  // beats the uniform walk.
+  int wl[kDepthBuckets];
+  bool use_buckets = false;
+  if (st == SDG_OK && best_choice >= kThreadTileChoices) {
+    static constexpr int kOpts[] = {8, 12, 16, 32, 64, -8, -12, -16, -24, -32};
+    const Plan& P = ctx->plan;
+    int present[kDepthBuckets] = {};
+    for (int k = 0; k < P.n_cells; ++k)
+      if (P.cell_depth[k] > 0) present[depth_bucket(P.cell_depth[k])] = 1;
+    for (int b = 0; b < kDepthBuckets; ++b) wl[b] = kTileLayerOptions[best_choice];
+    ctx->tile_choice = kBucketChoice;
+    ctx->xcd = best_xcd;
+    ctx->persistent = best_pers;
+    for (int b = 0; b < kDepthBuckets && st == SDG_OK; ++b) {
+      if (!present[b]) continue;
+      float bb = 1e30f;
+      int bo = wl[b];
+      for (int o : kOpts) {
+        wl[b] = o;
+        st = upload_bucket_table(ctx, wl, b);
+        float ms = 0.f;
+        if (st == SDG_OK) st = time_shape(&ms);
+        if (st != SDG_OK) break;
+        if (ms < bb) {
+          bb = ms;
+          bo = o;
+        }
+      }
+      wl[b] = bo;
+    }
+    float ms = 1e30f;
+    if (st == SDG_OK) st = upload_bucket_table(ctx, wl, -1);
+    if (st == SDG_OK) st = time_shape(&ms);
+    use_buckets = st == SDG_OK && ms < best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  ctx->tile_choice = best_choice;
+  ctx->tile_choice = use_buckets ? kBucketChoice : best_choice;
   ctx->xcd = best_xcd;
   ctx->persistent = best_pers;
+  if (use_buckets)
+    for (int b = 0; b < kDepthBuckets; ++b) ctx->walk_layers[b] = wl[b];
   ctx->graph_valid = false;
   if (st != SDG_OK) return st;
   if (chosen) {
-    chosen->tile_layers = kTileLayerOptions[best_choice];
-    chosen->xcd_remap = best_xcd;
-    chosen->persistent = best_pers;
+    sdg_status s2 = sdg_get_tuning(ctx, chosen);
+    if (s2 != SDG_OK) return s2;
   }
   g_err.clear();
   return SDG_OK;

@@ -52,20 +52,33 @@ struct DevMesh {
 // of one cell: (cell, first layer).  Tile heights from kWalkMinLayers up are
 // walked by one wavefront (the column-walk form of the stage kernel); the
 // smaller ones run one thread per prism.
+// nlay: layers of the tile (the walk covers layer0 .. layer0 + nlay - 1);
+// tile tables of one height list min(height, depth - layer0).
 struct WgTile {
   int32_t cell;
-  int32_t layer0;
+  uint16_t layer0;
+  uint16_t nlay;
 };
 constexpr int kTileChoices = 7;
 constexpr int kTileLayerOptions[kTileChoices] = {1, 2, 4, 8, 12, 16, 32};
 constexpr int kWalkMinLayers = 8;
 constexpr int kThreadTileChoices = 3;           // choices 0..2 run one thread per prism
+// The per-depth-bucket walk table (tile_layers 0 in sdg_tuning): every tile
+// is a walk of its own length, at most kBucketWalkMax layers.
+constexpr int kBucketChoice = kTileChoices;     // tile_choice of that table
+constexpr int kBucketWalkMax = 64;
+constexpr int kDepthBuckets = 6;
+// depth bucket of a cell of D layers: 1-8, 9-16, 17-24, 25-32, 33-48, > 48
+inline int depth_bucket(int D) {
+  return D <= 8 ? 0 : D <= 16 ? 1 : D <= 24 ? 2 : D <= 32 ? 3 : D <= 48 ? 4 : 5;
+}
 
 struct StageArgs {
   DevMesh m;
   const WgTile* tiles;   // one entry per workgroup: (cell, first layer)
   int32_t n_tiles;
-  int32_t tile_layers;   // layers per tile: 1, 2, 4 (blockDim 64 * tile_layers) or a walk segment
+  int32_t tile_layers;   // layers per tile: 1, 2, 4 (blockDim 64 * tile_layers), or >= 8: walks of
+                         // each tile's own length (kBucketWalkMax for the per-bucket table)
   int32_t xcd;           // 1: XCD-contiguous tile order
   int32_t persistent;    // 1: grid of resident workgroups walking the tiles
   int32_t n_cu;          // compute units of the device (persistent grid size)

@@ -641,7 +641,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a) {
 }
 
 // ===========================================================================
-// walk_kernel: one wavefront walks a cell's layers l0 .. l0 + tile_layers - 1.
+// walk_kernel: one wavefront walks a cell's layers l0 .. l0 + nlay - 1 of its tile.
 // ===========================================================================
 constexpr int kWalkLdsBytes = 40960;   // two layer slots; 4 wavefronts per CU
 
@@ -960,7 +960,7 @@ __global__ __launch_bounds__(64) void walk_kernel(StageArgs a) {
     wc.depth = (int)(((uint32_t)m.cell_base[cell + 1] - wc.base) / kCell);
     const int depth = wc.depth;
     const int l0 = tile.layer0;
-    const int l1 = min(l0 + a.tile_layers, depth);
+    const int l1 = l0 + tile.nlay;
     const size_t S = (size_t)m.n_slots;
     const size_t LS = (size_t)m.n_lslots;
     const uint32_t pc = wc.base + lane;
@@ -1047,8 +1047,8 @@ hipError_t launch_mode(const StageArgs& a, hipStream_t s) {
   const int threads = walk ? kCell : kCell * a.tile_layers;
   int grid = a.n_tiles;
   if (a.persistent) {
-    static std::atomic<int> cache[kTileChoices];
-    int ci = 0;
+    static std::atomic<int> cache[kTileChoices + 1];
+    int ci = kTileChoices;   // the per-bucket walk table
     for (int i = 0; i < kTileChoices; ++i)
       if (kTileLayerOptions[i] == a.tile_layers) ci = i;
     int per_cu = 1;

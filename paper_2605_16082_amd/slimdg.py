@@ -74,8 +74,12 @@ class Layout(ctypes.Structure):
     ]
 
 
+SDG_DEPTH_BUCKETS = 6
+
+
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile_layers", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+    _fields_ = [("tile_layers", ctypes.c_int32), ("xcd_remap", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("walk_layers", ctypes.c_int32 * SDG_DEPTH_BUCKETS)]
 
 
 class Params(ctypes.Structure):
@@ -332,16 +336,26 @@ class SlimDG:
 
     # -- launch shape, autotuning, graph replay -------------------------------
     def get_tuning(self) -> tuple[int, int, int]:
-        """(tile_layers, xcd_remap, persistent) of the stage kernel."""
+        """(tile_layers, xcd_remap, persistent) of the stage kernel; tile_layers
+        0 means walks segmented per depth bucket (``walk_layers``)."""
         t = Tuning()
         _check(self.lib.sdg_get_tuning(self.ctx, ctypes.byref(t)))
         return int(t.tile_layers), int(t.xcd_remap), int(t.persistent)
 
-    def set_tuning(self, tile_layers: int, xcd_remap: int = 1, persistent: int = 0):
-        t = Tuning(int(tile_layers), int(xcd_remap), int(persistent))
+    def walk_layers(self) -> list[int]:
+        """Per depth bucket walk segmentation (zeros unless tile_layers is 0)."""
+        t = Tuning()
+        _check(self.lib.sdg_get_tuning(self.ctx, ctypes.byref(t)))
+        return [int(v) for v in t.walk_layers]
+
+    def set_tuning(self, tile_layers: int, xcd_remap: int = 1, persistent: int = 0, walk_layers=None):
+        wl = (ctypes.c_int32 * SDG_DEPTH_BUCKETS)(*([0] * SDG_DEPTH_BUCKETS if walk_layers is None
+                                                     else [int(v) for v in walk_layers]))
+        t = Tuning(int(tile_layers), int(xcd_remap), int(persistent), wl)
         _check(self.lib.sdg_set_tuning(self.ctx, ctypes.byref(t)))
 
     def autotune(self, reps: int = 5) -> tuple[int, int, int]:
+        """Measure and keep the fastest launch shape; returns get_tuning()."""
         t = Tuning()
         _check(self.lib.sdg_autotune(self.ctx, int(reps), ctypes.byref(t)))
         return int(t.tile_layers), int(t.xcd_remap), int(t.persistent)

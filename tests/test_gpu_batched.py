@@ -91,12 +91,52 @@ def test_bad_tuning_rejected():
         assert e.value.status == -1, bad
 
 
+def test_bad_bucket_walks_rejected():
+    w, m = ensemble()
+    s = P.from_workload(w)[0]
+    for bad in ([8, 8, 8, 8, 8, 7], [8, 8, 65, 8, 8, 8], [-7, 8, 8, 8, 8, 8], [0] * 6):
+        with pytest.raises(P.SlimDGError) as e:
+            s.set_tuning(0, 1, 0, bad)
+        assert e.value.status == -1, bad
+
+
+# walk segmentations per depth bucket (1-8, 9-16, 17-24, 25-32, 33-48, > 48
+# layers): fixed lengths, balanced lengths (negative) and mixtures
+BUCKET_WALKS = [([8] * 6, 1, 0), ([-8] * 6, 0, 1), ([12, -12, 16, -16, 32, -24], 1, 1),
+                ([64, 64, 64, 64, 64, 64], 0, 0), ([-64, 9, -10, 13, -17, 33], 1, 0)]
+
+
+@pytest.mark.parametrize("precision", [P.SDG_FP64, P.SDG_FP32])
+def test_bucket_walks_do_not_change_results(precision):
+    """Per-depth-bucket walk tables give bitwise the stage outputs of the
+    2-layer one-thread-per-prism tile, on ragged z-level columns of 1-60
+    layers (cells of 17-60), the small ensemble (cells of 2-12) and a deep
+    uniform mesh where persistent workgroups walk many tiles."""
+    deep = W.ragged(seed=3, n=40, n_min=1, n_max=60, depth_max=300.0, n_fields=2)   # cells of 17-60 layers
+    assert deep.nlayers.min() <= 8 and deep.nlayers.max() > 48
+    for w in (deep, ensemble()[0], W.rotating_blob(n=60, n_layers=37, seed=5)):
+        s, U, kappa, state = P.from_workload(w, precision)
+        rng = np.random.default_rng(6)
+        Ts = s.scatter(w.T0 + 0.1 * rng.standard_normal(w.T0.shape))
+        s.set_tuning(2, 1, 0)
+        ref = [s.rk_stage(k, state, Ts) for k in range(3)]
+        for wl, x, pers in BUCKET_WALKS:
+            s.set_tuning(0, x, pers, wl)
+            assert s.get_tuning() == (0, x, pers) and s.walk_layers() == wl
+            outs = [s.rk_stage(k, state, Ts) for k in range(3)]
+            s.sync()
+            for a, b in zip(outs, ref):
+                assert torch_equal(a, b), (wl, x, pers)
+
+
 def test_autotune_keeps_results():
     w, m = ensemble()
     a = P.from_workload(w)
     b = P.from_workload(w)
     choice = a[0].autotune(reps=3)
-    assert choice[0] in (1, 2, 4, 8, 12, 16, 32) and choice[1] in (0, 1) and choice[2] in (0, 1)
+    assert choice[0] in (0, 1, 2, 4, 8, 12, 16, 32) and choice[1] in (0, 1) and choice[2] in (0, 1)
+    if choice[0] == 0:
+        assert all(8 <= abs(v) <= 64 for v in a[0].walk_layers())
     a[0].step(2)
     b[0].step(2)
     a[0].sync()
