@@ -57,9 +57,11 @@ def measured_traffic(tuning):
     m = re.search(r"stage_source_sha256:\s*([0-9a-f]{64})", txt)
     if not m or m.group(1) != stage_source_sha256():
         return None
-    pat = (r"traffic_bytes_mean_per_launch\[tile_layers=%d xcd_remap=%d persistent=%d\]:\s*([0-9.eE+]+)"
-           % (tuning["tile_layers"], tuning["xcd_remap"], tuning["persistent"]))
-    t = re.search(pat, txt)
+    key = "tile_layers=%d xcd_remap=%d persistent=%d" % (tuning["tile_layers"], tuning["xcd_remap"],
+                                                          tuning["persistent"])
+    if tuning.get("walk_layers"):
+        key += " walk_layers=" + ",".join(str(v) for v in tuning["walk_layers"])
+    t = re.search(r"traffic_bytes_mean_per_launch\[" + re.escape(key) + r"\]:\s*([0-9.eE+]+)", txt)
     return float(t.group(1)) if t else None
 
 

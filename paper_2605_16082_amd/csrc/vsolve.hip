@@ -31,10 +31,14 @@
 // without fields (factor_kernel) and kept in scratch; each solve's forward
 // sweep recomputes it in registers (its LU is needed for y) but stores only
 // y_l, and the back substitution reads the kept E_l.  That moves 18 values
-// per prism slot fewer than storing E with every solve.  Scratch values go
-// as 16-byte pairs.  The arithmetic type C is double (the FP64 and
-// FP32-state/FP64-solve forms) or float (the FP32-everywhere form); the
-// scratch then holds values of type C.
+// per prism slot fewer than storing E with every solve (FP64 solve 1.39 ->
+// 1.22 ms on 199,712 x 30 prisms, 4 fields).  Where the state has the solve's
+// type, y_l goes into the output rows themselves, where the back
+// substitution reads it and writes x_l over it (1.22 -> 1.17 ms: part of the
+// y traffic then stays in the cache); otherwise (float state, double solve)
+// into scratch.  Scratch values go as 16-byte pairs.  The arithmetic type C
+// is double (the FP64 and FP32-state/FP64-solve forms) or float (the
+// FP32-everywhere form); the scratch then holds values of type C.
 #include "internal.h"
 
 namespace sdg {
@@ -132,11 +136,15 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const C Jh = (C)m.geo[G_JH * m.n_col_slots + c];
   const C dt = (C)a.dt, eta = (C)a.eta;
   const double* __restrict__ kap = a.kappa;
-  const S* __restrict__ Tst = static_cast<const S*>(a.Tstar);
-  S* __restrict__ Tout = static_cast<S*>(a.Tout);
+  // T* and Tout may be the same array (an in-place solve), and the forward
+  // sweep writes y_l into Tout: no restrict on either
+  const S* Tst = static_cast<const S*>(a.Tstar);
+  S* Tout = static_cast<S*>(a.Tout);
   CPair<C>* __restrict__ Psc = reinterpret_cast<CPair<C>*>(a.scratch);   // E_l: pairs 0..8
   CPair<C>* __restrict__ Ysc = Psc + 9 * SL;                              // y_l: pairs 9..9+3NF-1
   constexpr int kNY = 6 * NF;        // y values per slot (even)
+  // y_l goes to the output rows (same type), read back and overwritten by x_l
+  constexpr bool kYOut = sizeof(S) == sizeof(C);
   const C sd = Jh * (C)(1.0 / 12.0), so = Jh * (C)(1.0 / 24.0);   // M_h diagonal / off-diagonal
 
   // ---------------- forward sweep ----------------
@@ -347,6 +355,11 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
 #pragma unroll
       for (int k = 0; k < 9; ++k)
         Psc[(size_t)k * SL + p] = CPair<C>{Ec[(2 * k) / 3][(2 * k) % 3], Ec[(2 * k + 1) / 3][(2 * k + 1) % 3]};
+    } else if (kYOut) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) Tout[(size_t)(f * 6 + i) * SL + p] = (S)yp[f][i];
     } else {
       C sv[kNY > 0 ? kNY : 2];
 #pragma unroll
@@ -393,11 +406,16 @@ __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
       sv[2 * k] = v.lo;
       sv[2 * k + 1] = v.hi;
     }
+    if (kYOut) {
 #pragma unroll
-    for (int k = 0; k < kNY / 2; ++k) {
-      const CPair<C> v = Ysc[(size_t)k * SL + p];
-      sv[18 + 2 * k] = v.lo;
-      sv[18 + 2 * k + 1] = v.hi;
+      for (int k = 0; k < kNY; ++k) sv[18 + k] = (C)Tout[(size_t)k * SL + p];
+    } else {
+#pragma unroll
+      for (int k = 0; k < kNY / 2; ++k) {
+        const CPair<C> v = Ysc[(size_t)k * SL + p];
+        sv[18 + 2 * k] = v.lo;
+        sv[18 + 2 * k + 1] = v.hi;
+      }
     }
     load_layer(m, lt0 + (size_t)l * kCell, g);
   };
