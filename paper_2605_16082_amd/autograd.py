@@ -3,7 +3,8 @@
 ``TracerSteps.apply(T0, kappa, model, n_steps, checkpoint_every)`` advances
 ``T0`` by ``n_steps`` library steps and returns the final state.  Its backward
 runs the library's adjoint step in reverse: the forward pass keeps only every
-``checkpoint_every``-th state; each segment is recomputed from its checkpoint
+``checkpoint_every``-th state (and the states of the last segment, which is
+reversed first); each earlier segment is recomputed from its checkpoint
 (storing the post-solve states it needs) and then reversed step by step.  The
 adjoint state is carried as Z = M^-1 lambda; the returned gradients are
 dJ/dT0 = M Z_0 and dJ/dkappa (per layer).  Both time schemes are reversed:
@@ -33,14 +34,24 @@ class TracerSteps(torch.autograd.Function):
         state = T0.detach().clone()
         model.set_fields(state)
         ckpts = []
+        last = None
         done = 0
         while done < n_steps:
             ckpts.append(state.clone())
             k = min(checkpoint_every, n_steps - done)
-            model.step(k)
+            if done + k == n_steps:
+                # the last segment's states are kept as they are computed: its
+                # reversal starts right away and needs no recomputation
+                last = [state.clone()]
+                for _ in range(k):
+                    model.step(1)
+                    last.append(state.clone())
+            else:
+                model.step(k)
             done += k
         ctx.model = model
         ctx.ckpts = ckpts
+        ctx.last = last
         ctx.n_steps = n_steps
         ctx.every = checkpoint_every
         ctx.kappa = kap
@@ -55,12 +66,16 @@ class TracerSteps(torch.autograd.Function):
         for i in range(len(ctx.ckpts) - 1, -1, -1):
             start = i * ctx.every
             k = min(ctx.every, ctx.n_steps - start)
-            st = ctx.ckpts[i].clone()
-            s.set_fields(st)
-            xs = [st.clone()]                    # states before step 0 .. after step k-1
-            for _ in range(k):
-                s.step(1)
-                xs.append(st.clone())
+            if i == len(ctx.ckpts) - 1 and ctx.last is not None:
+                xs = ctx.last                    # kept by the forward pass
+                ctx.last = None
+            else:
+                st = ctx.ckpts[i].clone()
+                s.set_fields(st)
+                xs = [st.clone()]                # states before step 0 .. after step k-1
+                for _ in range(k):
+                    s.step(1)
+                    xs.append(st.clone())
             for j in range(k - 1, -1, -1):
                 if getattr(s, "time_scheme", SDG_SCHEME_SSPRK3_LIE) == SDG_SCHEME_SPLIT_IMEX:
                     # the split-IMEX reverse step takes the state before the step
