@@ -393,19 +393,24 @@ __device__ __forceinline__ double penalty(double eta, double ka, double kb, doub
 //   Lo_l = dt [kappa_l Kv_l/2 - sig_u S ; -kappa_l Kv_l/2]          (6 x 3)
 //   Up_l = dt [-kappa_l Kv_l/2 ; kappa_l Kv_l/2 - sig_d S]          (6 x 3)
 // Block Thomas: D'_l = D_l^T - Lo_l G_{l-1}[3:6, :] (columns 0..2 only),
-// G_l = D'_l^-1 Up_l and y_l = D'_l^-1 (r_l - Lo_l y_{l-1}[3:6]) go to
-// scratch; back substitution mu_l = y_l - G_l mu_{l+1}[0:3].
+// G_l = D'_l^-1 Up_l and y_l = D'_l^-1 (r_l - Lo_l y_{l-1}[3:6]); back
+// substitution mu_l = y_l - G_l mu_{l+1}[0:3].  As in the forward solve, G_l
+// depends only on the mesh, kappa, dt and the penalty: a sweep without fields
+// (NF = 0) keeps it in its own array, each solve's forward sweep recomputes it
+// in registers and stores y_l into the output rows, and the back
+// substitution reads the kept G_l and overwrites y_l with mu_l.
 struct TSolveArgs {
   DevMesh m;
-  const double* Z;
+  const double* Z;     // may be the same array as mu
   double* mu;
   const double* kappa;
-  double* scratch;    // [18 + 6F][n_slots]
+  double* gfac;        // [18][n_slots]: the kept G_l
   double dt, eta;
 };
 
 template <int NF>
 __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
+  constexpr int kF = NF > 0 ? NF : 1;   // array extent (the factor sweep has no fields)
   const DevMesh& m = a.m;
   const int cell = xcd_tile(blockIdx.x, m.n_cells);
   const int lane = threadIdx.x;
@@ -418,8 +423,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
   const double Jh = m.geo[G_JH * m.n_col_slots + c];
   const double dt = a.dt, eta = a.eta;
   const double* __restrict__ kap = a.kappa;
-  double* __restrict__ Gsc = a.scratch;
-  double* __restrict__ Ysc = a.scratch + 18 * SL;
+  double* __restrict__ Gsc = a.gfac;
   const double sd = Jh * (1.0 / 12.0), so = Jh * (1.0 / 24.0);
 
   LayerGeo gc, gn, gp;
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
   double kvc[6];
   vertical_stiffness(gc, Jh, kvc);
   double Gp[6][3];
-  double yp[NF][6];
+  double yp[kF][6];
   double kp = 0.0;
   gp = gc;
   for (int l = 0; l < N; ++l) {
@@ -467,7 +471,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
         d[i + 3][j + 3] = BB;
       }
     // right-hand sides r = M Z
-    double r[NF][6];
+    double r[kF][6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       double t[6];
@@ -574,7 +578,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
 #pragma unroll
       for (int i = 0; i < 6; ++i) {
         yp[f][i] = z[i];
-        Ysc[(size_t)(f * 6 + i) * SL + p] = z[i];
+        a.mu[(size_t)(f * 6 + i) * SL + p] = z[i];   // Z_l has been read: y_l may overwrite it
       }
     }
 #pragma unroll
@@ -582,7 +586,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         Gp[i][q] = Gc[i][q];
-        Gsc[(size_t)(i * 3 + q) * SL + p] = Gc[i][q];
+        if (NF == 0) Gsc[(size_t)(i * 3 + q) * SL + p] = Gc[i][q];
       }
     kp = kc;
     gp = gc;
@@ -591,8 +595,9 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
       vertical_stiffness(gc, Jh, kvc);
     }
   }
+  if (NF == 0) return;
   // back substitution
-  double xn[NF][6];
+  double xn[kF][6];
   {
     const size_t p = p0 + (size_t)(N - 1) * kCell;
 #pragma unroll
@@ -615,7 +620,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
       double xt[3] = {xn[f][0], xn[f][1], xn[f][2]};
 #pragma unroll
       for (int i = 0; i < 6; ++i)
-        xn[f][i] = Ysc[(size_t)(f * 6 + i) * SL + p] - (G[i][0] * xt[0] + G[i][1] * xt[1] + G[i][2] * xt[2]);
+        xn[f][i] = a.mu[(size_t)(f * 6 + i) * SL + p] - (G[i][0] * xt[0] + G[i][1] * xt[1] + G[i][2] * xt[2]);
 #pragma unroll
       for (int i = 0; i < 6; ++i) a.mu[(size_t)(f * 6 + i) * SL + p] = xn[f][i];
     }
@@ -890,17 +895,21 @@ hipError_t launch_adjoint_stage(const DevMesh& m, const WgTile* tiles, int n_til
 }
 
 hipError_t launch_tsolve(const DevMesh& m, int n_fields, const double* Z, double* mu, const double* kappa,
-                         double* scratch, double dt, double eta, hipStream_t s) {
+                         double* gfac, double dt, double eta, bool factor, hipStream_t s) {
   if (m.n_cells == 0) return hipSuccess;
   TSolveArgs a{};
   a.m = m;
   a.Z = Z;
   a.mu = mu;
   a.kappa = kappa;
-  a.scratch = scratch;
+  a.gfac = gfac;
   a.dt = dt;
   a.eta = eta;
   dim3 grid(m.n_cells), block(kCell);
+  if (factor) {
+    hipLaunchKernelGGL((tsolve_kernel<0>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   switch (n_fields) {
     case 1: hipLaunchKernelGGL((tsolve_kernel<1>), grid, block, 0, s, a); break;
     case 2: hipLaunchKernelGGL((tsolve_kernel<2>), grid, block, 0, s, a); break;

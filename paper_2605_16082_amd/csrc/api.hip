@@ -50,6 +50,7 @@ struct Plan {
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_tiles_bucket, o_stage_a, o_stage_b, o_scratch,
+      o_tfac,
       o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, total;
   size_t state_bytes, velocity_bytes;
 };
@@ -191,6 +192,7 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_stage_a = take(P.state_bytes);
   P.o_stage_b = take(P.state_bytes);
   P.o_scratch = take(sizeof(double) * (size_t)(18 + 6 * P.F) * (size_t)P.n_slots);
+  P.o_tfac = take(sizeof(double) * 18 * (size_t)P.n_slots);   // the adjoint's transposed factors
   P.o_colmass = take(sizeof(double) * (size_t)P.F * P.CS);
   P.o_msum = take(sizeof(double) * (size_t)P.F * P.n_members);
   P.o_flag = take(sizeof(int32_t) * 64);
@@ -281,9 +283,13 @@ struct sdg_ctx {
   void* stage_a = nullptr;
   void* stage_b = nullptr;
   double* scratch = nullptr;
-  // the solve scratch holds the block-Thomas factors of (kappa, efac_dt, eta)
+  // the solve scratch holds the block-Thomas factors of (kappa, efac_dt, eta),
+  // tfac those of the transposed system for tfac_dt
   bool efac_valid = false;
   double efac_dt = 0.0;
+  double* tfac = nullptr;
+  bool tfac_valid = false;
+  double tfac_dt = 0.0;
   // state set by the caller
   bool have_params = false;
   double dt = 0.0, eta = 4.0;
@@ -392,6 +398,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   ctx->kh_scale = 0.0;
   ctx->graph_valid = false;
   ctx->efac_valid = false;
+  ctx->tfac_valid = false;
   ctx->U = nullptr;
   ctx->kappa = nullptr;
   ctx->state = nullptr;
@@ -521,6 +528,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   ctx->stage_a = ws + Q.o_stage_a;
   ctx->stage_b = ws + Q.o_stage_b;
   ctx->scratch = reinterpret_cast<double*>(ws + Q.o_scratch);
+  ctx->tfac = reinterpret_cast<double*>(ws + Q.o_tfac);
   ctx->have_mesh = true;
   g_err.clear();
   return SDG_OK;
@@ -558,6 +566,7 @@ sdg_status sdg_set_params(sdg_ctx* ctx, const sdg_params* p) {
   ctx->check_finite = p->check_finite != 0;
   ctx->graph_valid = false;
   ctx->efac_valid = false;
+  ctx->tfac_valid = false;
   ctx->have_params = true;
   g_err.clear();
   return SDG_OK;
@@ -578,6 +587,7 @@ sdg_status sdg_set_diffusivity(sdg_ctx* ctx, const double* dev_kappa) {
   ctx->kappa = dev_kappa;
   ctx->graph_valid = false;
   ctx->efac_valid = false;
+  ctx->tfac_valid = false;
   g_err.clear();
   return SDG_OK;
 }
@@ -688,6 +698,17 @@ sdg_status ensure_factors(sdg_ctx* ctx, double dt, hipStream_t strm) {
   if (e != hipSuccess) return hip_fail(e, "column factor launch");
   ctx->efac_valid = true;
   ctx->efac_dt = dt;
+  return SDG_OK;
+}
+
+// The transposed system's factors for the adjoint's solve over dt, kept in
+// their own array (the forward factors stay valid).
+sdg_status ensure_tfactors(sdg_ctx* ctx, double dt, hipStream_t strm) {
+  if (ctx->tfac_valid && ctx->tfac_dt == dt) return SDG_OK;
+  hipError_t e = launch_tsolve(ctx->dm, ctx->plan.F, nullptr, nullptr, ctx->kappa, ctx->tfac, dt, ctx->eta, true, strm);
+  if (e != hipSuccess) return hip_fail(e, "transposed column factor launch");
+  ctx->tfac_valid = true;
+  ctx->tfac_dt = dt;
   return SDG_OK;
 }
 
@@ -1159,9 +1180,10 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   const WgTile* tiles = ctx->tiles[choice];
   const int nt = P.n_tiles[choice];
   hipStream_t s = ctx->stream;
-  ctx->efac_valid = false;   // the transposed solve reuses the solve scratch
+  sdg_status fst = ensure_tfactors(ctx, ctx->dt, s);
+  if (fst != SDG_OK) return fst;
   hipError_t e = launch_tsolve(ctx->dm, P.F, static_cast<const double*>(dev_z_next), mu, ctx->kappa,
-                               ctx->scratch, ctx->dt, ctx->eta, s);
+                               ctx->tfac, ctx->dt, ctx->eta, false, s);
   if (e != hipSuccess) return hip_fail(e, "transposed solve launch");
   if (dev_dkappa) {
     e = launch_kappa_gradient(ctx->dm, P.F, mu, static_cast<const double*>(dev_x_next), ctx->kpart, ctx->eta,
@@ -1235,8 +1257,11 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
                            0.0, s);
   if (e == hipSuccess) e = enqueue_hdiff(ctx, Z1, w, nullptr, 2.0 * h, 0.0, s);
   // mu' = (M - h A^T)^-1 M w;  dJ/dkappa_l += h mu'^T A_l x_h
-  ctx->efac_valid = false;   // the transposed solve reuses the solve scratch
-  if (e == hipSuccess) e = launch_tsolve(ctx->dm, P.F, w, mu, ctx->kappa, ctx->scratch, h, ctx->eta, s);
+  if (e == hipSuccess) {
+    sdg_status fst = ensure_tfactors(ctx, h, s);
+    if (fst != SDG_OK) return fst;
+    e = launch_tsolve(ctx->dm, P.F, w, mu, ctx->kappa, ctx->tfac, h, ctx->eta, false, s);
+  }
   if (e == hipSuccess && dev_dkappa)
     e = launch_kappa_gradient(ctx->dm, P.F, mu, out, ctx->kpart, ctx->eta, h, dev_dkappa, s);
   // Z0 = mu' + h L~ mu' + Z1 - w

@@ -150,8 +150,11 @@ hipError_t launch_adjoint_stage(const DevMesh& m, const WgTile* tiles, int n_til
                                 int n_fields, bool w_zero, const double* Y, const double* X1, const double* X2,
                                 double* out, const double* U, double dt, double b, double a1, double a2,
                                 hipStream_t s);
+// factor = true: compute and keep the transposed block-Thomas factors G_l for
+// (kappa, dt, eta) in gfac ([18][n_slots]); false: mu from Z with the kept
+// factors (mu may be Z).
 hipError_t launch_tsolve(const DevMesh& m, int n_fields, const double* Z, double* mu, const double* kappa,
-                         double* scratch, double dt, double eta, hipStream_t s);
+                         double* gfac, double dt, double eta, bool factor, hipStream_t s);
 hipError_t launch_kappa_gradient(const DevMesh& m, int n_fields, const double* mu, const double* x,
                                  double* partial, double eta, double dt, double* dkappa, hipStream_t s);
 hipError_t launch_mass_apply(const DevMesh& m, const void* X, void* Y, int n_fields, bool fp32, bool inverse,
