@@ -188,17 +188,25 @@ def forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None):
     return xs
 
 
-def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None, return_scale=False):
+def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h=None, return_scale=False,
+             xs=None):
     """(J, dJ/dT0 of shape (F, 6, P), dJ/dkappa of shape (len(kappa),)).
     With per-column kappa_h the explicit operator also holds the horizontal
     diffusion matrix D (linear, so it adds D to R_lin).
 
     With return_scale, also the size of the sum behind each dJ/dkappa_l:
     sum_n dt |mu_n|^T |A_l| |x^{n+1}|, the sum of its terms' magnitudes, which
-    bounds how far rounding in the terms can move the (cancelling) total."""
+    bounds how far rounding in the terms can move the (cancelling) total.
+
+    xs: the forward states x^0 .. x^N when the caller has them already (from
+    ``forward`` or from ``parallel.run_steps(..., states=True)``, which
+    evaluates the same step); otherwise ``forward`` computes them."""
     kappa = np.asarray(kappa, dtype=np.float64)
     F = T0.shape[0]
-    xs = forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta, kappa_h)
+    if xs is None:
+        xs = forward(mesh, U, kappa, T0, dt, t_ext, n_steps, eta, kappa_h)
+    if len(xs) != n_steps + 1:
+        raise ValueError("xs must hold the n_steps + 1 states x^0 .. x^N")
     M = mass_matrix_global(mesh)
     R = advection_matrix(mesh, U)
     if kappa_h is not None:
@@ -207,7 +215,7 @@ def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h
     Minv_R = (mass_inverse_global(mesh) @ R).tocsr()     # L = M^-1 R, M block-diagonal
     Lt = Minv_R.T.tocsr()                                   # L^T
     A = vertical_matrix_global(mesh, kappa, eta)
-    K_T = (M - dt * A).T.tocsc()
+    K_T = spla.splu((M - dt * A).T.tocsc())               # factored once, solved every step
     A_l = []
     for l in range(len(kappa)):
         e = np.zeros_like(kappa)
@@ -220,7 +228,7 @@ def gradient(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, eta=4.0, kappa_h
     dk = np.zeros_like(kappa)
     dk_abs = np.zeros_like(kappa)
     for n in range(n_steps - 1, -1, -1):
-        mu = spla.spsolve(K_T, lam).reshape(lam.shape)
+        mu = K_T.solve(lam).reshape(lam.shape)
         x1 = _flat(xs[n + 1])
         for l in range(len(kappa)):
             dk[l] += dt * np.sum(mu * (A_l[l] @ x1))

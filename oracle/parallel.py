@@ -82,10 +82,11 @@ def _column_ranges(mesh):
 
 
 def run_steps(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, scheme="lie", eta=4.0, kappa_h=None,
-              workers=8, log=None):
+              workers=8, log=None, states=False):
     """n_steps of the oracle step ('lie': SSP-RK3 then the vertical solve,
     as ``prism_dg.step``; 'imex': ``split_imex.imex_step``) from T0 (F, 6, P),
-    evaluated by ``workers`` forked processes; returns the final state."""
+    evaluated by ``workers`` forked processes; returns the final state, or
+    with states=True the list of every state x^0 .. x^N."""
     F = T0.shape[0]
     shape = (F, 6, mesh.P)
     _G.clear()
@@ -99,6 +100,7 @@ def run_steps(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, scheme="lie", e
     columns = _column_ranges(mesh)
     ctx = mp.get_context("fork")
     t0 = time.time()
+    kept = [np.array(T0, dtype=np.float64)] if states else None
     with ctx.Pool(workers) as pool:
         for n in range(n_steps):
             if scheme == "lie":
@@ -117,8 +119,10 @@ def run_steps(mesh: PrismMesh, U, kappa, T0, dt, t_ext, n_steps, scheme="lie", e
                 _G["X"][:] = _G["Y"]
             else:
                 raise ValueError(scheme)
+            if states:
+                kept.append(np.array(_G["X"]))
             if log:
                 log(f"oracle step {n + 1}/{n_steps} done ({time.time() - t0:.0f} s)")
-    out = np.array(_G["X"])
+    out = kept if states else np.array(_G["X"])
     _G.clear()
     return out
