@@ -335,8 +335,9 @@ sdg_status sdg_m_dot(sdg_ctx* ctx, const void* dev_X, const void* dev_Y, double*
  *            horizontal diffusion D when okubo_scale > 0, D^T = D)
  * so that lambda^n = M Z^n.  dev_z_next, dev_z_out: [n_fields][6][n_slots]
  * doubles (may alias); dev_x_next: the state after the forward step being
- * reversed; dev_dkappa: [max_layers] doubles, accumulated.  Uses the
- * workspace stage buffers. */
+ * reversed, which with dev_dkappa must not be dev_z_out (SDG_E_ARG);
+ * dev_dkappa: [max_layers] doubles, accumulated.  Uses the workspace stage
+ * buffers. */
 sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_next,
                             double* dev_dkappa);
 

@@ -1162,6 +1162,8 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint needs sdg_set_diffusivity");
   if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint: NULL buffer");
   if (dev_dkappa && !dev_x_next) return fail(SDG_E_ARG, "sdg_step_adjoint: dkappa needs x_next");
+  if (dev_dkappa && dev_x_next == dev_z_out)
+    return fail(SDG_E_ARG, "sdg_step_adjoint: x_next must not be z_out (the solve overwrites z_out before x_next is read)");
   if (dev_z_out == ctx->stage_a || dev_z_out == ctx->stage_b || dev_z_next == ctx->stage_a || dev_z_next == ctx->stage_b)
     return fail(SDG_E_ARG, "sdg_step_adjoint: buffers must not be the workspace stage buffers");
   DeviceGuard g(ctx->device);

@@ -66,6 +66,21 @@ def test_mass_apply_and_m_dot():
     assert abs(md - float(np.einsum("fin,fin->", ref, w.T0))) <= 1e-12 * abs(md)
 
 
+def test_adjoint_rejects_x_next_written_by_the_solve():
+    """With dkappa the kappa gradient reads x_next after the transposed solve
+    has overwritten z_out, so the two may not be one buffer; the call fails
+    before any launch."""
+    import torch
+    w, m = _case("tiny")
+    s, U, kappa, state = P.from_workload(w)
+    z = s.new_state()
+    dk = torch.zeros(64, dtype=torch.float64, device=s.device)
+    with pytest.raises(P.SlimDGError):
+        s.step_adjoint(z, z, z, dk)
+    s.step_adjoint(z, z, z, None)          # without dkappa x_next is not read
+    s.sync()
+
+
 @pytest.mark.parametrize("name", ["tiny", "ragged", "rotating_blob"])
 def test_adjoint_gradient_matches_oracle(name):
     w, m = _case(name)
