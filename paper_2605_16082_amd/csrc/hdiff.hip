@@ -120,12 +120,6 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
   const int li = threadIdx.x / kCell;
   const bool live = l < m.nlay[c];
   const int64_t p = (int64_t)m.cell_base[cell] + lane + (int64_t)l * kCell;
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < 6 * NF; ++r) sh[r][li][lane] = Ts[(size_t)r * S + (size_t)p];
-  }
-  __syncthreads();
-  if (!live) return;
   const int CS = m.n_col_slots;
   const R* geo = geo_rows<R>(m);
   const R* zl = level_rows<R>(m);
@@ -134,6 +128,8 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
   R* Out2 = static_cast<R*>(a.Tout2);
   const R c1 = R(a.c1), c2 = R(a.c2);
 
+  // per-column data first (every column slot is in bounds), so that its
+  // loads are in flight together with the staging loads below
   R gl[3][2], Jh;
   lambda_grads<R>(geo, CS, c, gl, Jh);
   const R kh = R(a.kh[c]);
@@ -163,10 +159,16 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
   }
 
   const int64_t lt = (int64_t)m.cell_lbase[cell] + lane + (int64_t)l * kCell;
-  {
-    R dz[3];
+  R dz[3] = {R(0), R(0), R(0)};
+  if (live) {
 #pragma unroll
     for (int v = 0; v < 3; ++v) dz[v] = zl[v * LS + (size_t)lt] - zl[v * LS + (size_t)(lt + kCell)];
+#pragma unroll
+    for (int r = 0; r < 6 * NF; ++r) sh[r][li][lane] = Ts[(size_t)r * S + (size_t)p];
+  }
+  __syncthreads();
+  if (!live) return;
+  {
     // volume factor kh int_K z_zeta J_h dxi deta = kh J_h (dz_0 + dz_1 + dz_2) / 12
     const R vf = kh * Jh * (dz[0] + dz[1] + dz[2]) * R(1.0 / 12.0);
     // Mz^-1 = sc * cofactors of m (Mz = J_h/120 m), M^-1 = [2 -1; -1 2] (x) Mz^-1
