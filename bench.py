@@ -239,11 +239,37 @@ def column_dv_form(w, torch, P_mod, reps=20):
     return out
 
 
+OCEAN_REFERENCE = os.path.join(ROOT, "tests", "golden", "four_field_ocean_100steps.npz")
+
+
+def oracle_sampled_errors(torch, s, x, reference):
+    """Per field: max over the stored oracle samples of |x - x_oracle| / max
+    |x_oracle| (x on the device, the samples in natural order i * P + p)."""
+    flat = x[:, :, s.slots].double().reshape(x.shape[0], -1)
+    out = []
+    for f in range(x.shape[0]):
+        idx = torch.as_tensor(reference["idx"][f], device=x.device)
+        got = flat[f].index_select(0, idx).cpu().numpy()
+        out.append(float(np.abs(got - reference["vals"][f]).max() / reference["fmax"][f]))
+    return out
+
+
 def precision_forms(w, steps, torch, P_mod):
     """The precision forms after `steps` steps from the same initial state:
-    per-field max-norm error against the FP64 path (which matches the FP64
-    oracle to 1e-12 stage by stage and solve by solve), the difference of
-    each field's total mass over (max |T_f| * volume), and the time per step."""
+    per-field max-norm error against the FP64 GPU path, the difference of
+    each field's total mass over (max |T_f| * volume), and the time per step.
+    With the stored FP64 oracle reference of this run (written by
+    tests/golden/make_four_field_ocean_reference.py: 20,000 sampled entries
+    per field, each field's maximum and mass), also every form's error against
+    the oracle on those samples and its mass drift against the oracle's mass;
+    the full-field error of a float form against the oracle is then at most
+    its full-field error against the FP64 path plus the FP64 path's own
+    (sampled) error against the oracle."""
+    reference = None
+    if os.path.exists(OCEAN_REFERENCE):
+        ref_npz = np.load(OCEAN_REFERENCE)
+        if int(ref_npz["steps"]) == steps:
+            reference = ref_npz
     s, U, kappa, x = P_mod.from_workload(w, P_mod.SDG_FP64)
     s.autotune(reps=2)
     s.step(1)
@@ -253,6 +279,12 @@ def precision_forms(w, steps, torch, P_mod):
     m_ref = s.mass(ref)
     vol = unit_mass(s)
     out = {"steps": steps, "fp64": {"ms_per_step": t / steps * 1e3}}
+    if reference is not None:
+        out["oracle_reference"] = "tests/golden/four_field_ocean_100steps.npz (sampled)"
+        out["fp64"]["max_rel_err_per_field_vs_oracle_sampled"] = oracle_sampled_errors(torch, s, x, reference)
+        # |m - m_oracle| / (max |T_f| * volume), as mass_err_per_field
+        oscale = np.asarray(reference["fmax"]) * float(vol[0, 0])
+        out["fp64"]["mass_drift_vs_oracle"] = (np.abs(m_ref[0] - reference["mass"]) / oscale).tolist()
     del s, U, kappa, x
     for key, prec in (("fp32_state_fp64_solve", P_mod.SDG_FP32_STATE_FP64_SOLVE),
                       ("fp32_everywhere", P_mod.SDG_FP32)):
@@ -266,6 +298,12 @@ def precision_forms(w, steps, torch, P_mod):
             "max_rel_err_per_field": field_errors(torch, x, ref),
             "mass_err_per_field": mass_errors(torch, s.mass(x), m_ref, ref, vol)[0].tolist(),
         }
+        if reference is not None:
+            e64 = out["fp64"]["max_rel_err_per_field_vs_oracle_sampled"]
+            out[key]["max_rel_err_per_field_vs_oracle_sampled"] = oracle_sampled_errors(torch, s, x, reference)
+            out[key]["max_rel_err_per_field_vs_oracle_bound"] = [a + b for a, b in
+                                                                 zip(out[key]["max_rel_err_per_field"], e64)]
+            out[key]["mass_drift_vs_oracle"] = (np.abs(s.mass(x)[0] - reference["mass"]) / oscale).tolist()
         del s, U, kappa, x
     del ref
     torch.cuda.empty_cache()

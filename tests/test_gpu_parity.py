@@ -317,3 +317,46 @@ def test_walk_shapes_with_vertical_velocity(name):
         else:
             for k, (g, b) in enumerate(zip(got, base)):
                 assert np.array_equal(g, b), (shape, k)
+
+
+def _ocean_reference():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "four_field_ocean_100steps.npz")
+    return np.load(path)
+
+
+def test_four_field_ocean_100_steps_against_oracle(big):
+    """The four-field ocean (199,712 x 30, 4 fields) after 100 FP64 steps in the
+    benchmark's launch shape, against the oracle's state stored by
+    tests/golden/make_four_field_ocean_reference.py: 20,000 sampled entries per
+    field within 1e-12 of the field's maximum, and each field's total mass
+    within 1e-12 of max |T_f| times the volume."""
+    ref = _ocean_reference()
+    w, m = big
+    s, U, kappa, state = upload(w)
+    print("tuning", s.autotune(reps=2))
+    s.scatter(w.T0, out=state)
+    n = int(ref["steps"])
+    s.step(n)
+    s.sync()
+    flat = state[:, :, s.slots].reshape(w.n_fields, -1)        # natural order, index i * P + p
+    for f in range(w.n_fields):
+        idx = torch_index(ref["idx"][f], state.device)
+        got = flat[f].index_select(0, idx).double().cpu().numpy()
+        err = np.abs(got - ref["vals"][f]).max() / ref["fmax"][f]
+        print("field", f, "sampled error", err)
+        assert err <= TOL64, (f, err)
+    # each field's mass against the oracle's, relative to max |T_f| times the
+    # volume (u and v have totals near zero)
+    mass = s.mass(state)[0]
+    one = s.new_state()
+    one[:, :, s.slots] = 1.0
+    vol = s.mass(one)[0, 0]
+    drift = np.abs(mass - ref["mass"]) / (ref["fmax"] * vol)
+    print("mass", mass, ref["mass"], "drift", drift)
+    assert np.all(drift <= 1e-12), drift
+
+
+def torch_index(idx, device):
+    import torch
+    return torch.as_tensor(np.asarray(idx, dtype=np.int64), device=device)
