@@ -16,9 +16,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 @pytest.mark.slow
 def test_abi_under_address_and_ub_sanitizers():
     sys.path.insert(0, ROOT)
+    import glob
     from paper_2605_16082_amd import build as B
-    if not os.path.exists(B.ASAN_LIB):
-        B.build_sanitized()
+    sources = glob.glob(os.path.join(B.CSRC, "*")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    if not os.path.exists(B.ASAN_LIB) or os.path.getmtime(B.ASAN_LIB) < max(map(os.path.getmtime, sources)):
+        B.build_sanitized()          # absent or older than a source
     env = dict(os.environ)
     env.update(LD_PRELOAD=B.asan_runtime(), SLIMDG_LIB=B.ASAN_LIB,
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
