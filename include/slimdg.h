@@ -78,7 +78,7 @@
 extern "C" {
 #endif
 
-#define SDG_ABI_VERSION 7
+#define SDG_ABI_VERSION 8
 #define SDG_CELL_COLUMNS 64
 #define SDG_MAX_FIELDS 4
 
@@ -377,6 +377,22 @@ sdg_status sdg_column_dv_solve(sdg_ctx* ctx, int kind, int n_comp, const void* d
  * doubles, accumulated.  Uses the workspace stage buffers. */
 sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_prev,
                                  double* dev_dkappa);
+
+/* One split-IMEX step of the set fields, as sdg_step(ctx, 1) (contexts with
+ * SDG_SCHEME_SPLIT_IMEX only, SDG_E_UNSUPPORTED otherwise), whose vertically
+ * implicit half-step state x_h (the section 3 two-step scheme's first step)
+ * is left in dev_x_half ([n_fields][6][n_slots] in the state precision)
+ * rather than in the workspace: the state the reverse step pairs with the
+ * kappa gradient.  dev_x_half must not be the set fields (SDG_E_ARG).
+ * Enqueued on the context stream; does not synchronise. */
+sdg_status sdg_step_keep_half(sdg_ctx* ctx, void* dev_x_half);
+
+/* sdg_step_adjoint_imex given the reversed step's x_h (as left by
+ * sdg_step_keep_half) instead of the state before it, so that x_h is not
+ * rebuilt: the same result with one explicit half step and one column solve
+ * fewer.  dev_z_out must not alias dev_z_next or dev_x_half. */
+sdg_status sdg_step_adjoint_imex_half(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_half,
+                                      double* dev_dkappa);
 
 /* Wait for the context's stream and report any asynchronous HIP error. */
 sdg_status sdg_sync(sdg_ctx* ctx);

@@ -5,11 +5,12 @@
 runs the library's adjoint step in reverse: the forward pass keeps only every
 ``checkpoint_every``-th state (and the states of the last segment, which is
 reversed first); each earlier segment is recomputed from its checkpoint
-(storing the post-solve states it needs) and then reversed step by step.  The
-adjoint state is carried as Z = M^-1 lambda; the returned gradients are
+(storing the states it needs) and then reversed step by step.  The adjoint
+state is carried as Z = M^-1 lambda; the returned gradients are
 dJ/dT0 = M Z_0 and dJ/dkappa (per layer).  Both time schemes are reversed:
-SSP-RK3 + Lie with the state after each step, split-IMEX with the state
-before it.
+SSP-RK3 + Lie with the state after each step, split-IMEX with each step's
+vertically implicit half-step state x_h (kept by ``step_keep_half``, so the
+reverse step need not rebuild it).
 
 ``MNorm.apply(x, model)`` is J = sqrt(sum_f x_f^T M x_f), whose gradient is
 M x / J.  Both use only library kernels on the device.
@@ -22,6 +23,28 @@ import math
 import torch
 
 from .slimdg import SDG_SCHEME_SPLIT_IMEX, SDG_SCHEME_SSPRK3_LIE
+
+
+def _imex(model) -> bool:
+    return getattr(model, "time_scheme", SDG_SCHEME_SSPRK3_LIE) == SDG_SCHEME_SPLIT_IMEX
+
+
+def _segment_states(model, state, k):
+    """k steps of `model` on its set fields `state`, keeping what their
+    reversal needs: SSP-RK3 + Lie, the states before step 0 .. after step
+    k-1 (k + 1 of them); split-IMEX, each step's half-step state x_h (k)."""
+    if _imex(model):
+        xs = []
+        for _ in range(k):
+            xh = torch.empty_like(state)
+            model.step_keep_half(xh)
+            xs.append(xh)
+        return xs
+    xs = [state.clone()]
+    for _ in range(k):
+        model.step(1)
+        xs.append(state.clone())
+    return xs
 
 
 class TracerSteps(torch.autograd.Function):
@@ -42,10 +65,7 @@ class TracerSteps(torch.autograd.Function):
             if done + k == n_steps:
                 # the last segment's states are kept as they are computed: its
                 # reversal starts right away and needs no recomputation
-                last = [state.clone()]
-                for _ in range(k):
-                    model.step(1)
-                    last.append(state.clone())
+                last = _segment_states(model, state, k)
             else:
                 model.step(k)
             done += k
@@ -72,15 +92,12 @@ class TracerSteps(torch.autograd.Function):
             else:
                 st = ctx.ckpts[i].clone()
                 s.set_fields(st)
-                xs = [st.clone()]                # states before step 0 .. after step k-1
-                for _ in range(k):
-                    s.step(1)
-                    xs.append(st.clone())
+                xs = _segment_states(s, st, k)
             for j in range(k - 1, -1, -1):
-                if getattr(s, "time_scheme", SDG_SCHEME_SSPRK3_LIE) == SDG_SCHEME_SPLIT_IMEX:
-                    # the split-IMEX reverse step takes the state before the step
+                if _imex(s):
+                    # the split-IMEX reverse step takes that step's x_h
                     zn = torch.empty_like(z)
-                    s.step_adjoint_imex(z, zn, xs[j], dk)
+                    s.step_adjoint_imex_half(z, zn, xs[j], dk)
                     z = zn
                 else:
                     s.step_adjoint(z, z, xs[j + 1], dk)

@@ -730,19 +730,22 @@ sdg_status enqueue_solve(sdg_ctx* ctx, const void* Tstar, void* Tout, double dt,
 //   X <- B + 2 (x_h + dt/2 M^-1 R(x_h))                    explicit full step
 // The last line is x_0 + 2 (x_h - y) + dt M^-1 R(x_h), and 2 (x_h - y) is
 // dt M^-1 A x_h by the half step's own system.
-sdg_status enqueue_imex_step(sdg_ctx* ctx, hipStream_t strm) {
+// With xh, the half step's solve writes x_h there (the caller's buffer)
+// instead of back into the stage buffer, and the second stage reads it there.
+sdg_status enqueue_imex_step(sdg_ctx* ctx, hipStream_t strm, void* xh = nullptr) {
   void* X = ctx->state;
   void* A = ctx->stage_a;
   void* B = ctx->stage_b;
+  void* H = xh ? xh : A;
   const double h = 0.5 * ctx->dt;
   StageArgs s1 = stage_args(ctx, nullptr, X, A, 0.0, 1.0, h);
   s1.Tout2 = B;
   hipError_t e = launch_stage(s1, ctx->plan.fp32, ctx->w_zero, false, false, strm);
   if (e == hipSuccess) e = hdiff_after_stage(ctx, s1, h, -2.0 * h, strm);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX half step launch");
-  sdg_status st = enqueue_solve(ctx, A, A, h, strm);
+  sdg_status st = enqueue_solve(ctx, A, H, h, strm);
   if (st != SDG_OK) return st;
-  StageArgs s2 = stage_args(ctx, B, A, X, 1.0, 2.0, h);
+  StageArgs s2 = stage_args(ctx, B, H, X, 1.0, 2.0, h);
   e = launch_stage(s2, ctx->plan.fp32, ctx->w_zero, false, true, strm);
   if (e == hipSuccess) e = hdiff_after_stage(ctx, s2, 2.0 * h, 0.0, strm);
   if (e != hipSuccess) return hip_fail(e, "split-IMEX full step launch");
@@ -824,6 +827,22 @@ sdg_status sdg_step(sdg_ctx* ctx, int n_steps) {
     if (e != hipSuccess) return hip_fail(e, "finite check");
     if (h) return fail(SDG_E_NUMERIC, "non-finite values in the state after %d steps", n_steps);
   }
+  g_err.clear();
+  return SDG_OK;
+}
+
+sdg_status sdg_step_keep_half(sdg_ctx* ctx, void* dev_x_half) {
+  sdg_status st = check_explicit(ctx, "sdg_step_keep_half");
+  if (st != SDG_OK) return st;
+  if (ctx->scheme != SDG_SCHEME_SPLIT_IMEX)
+    return fail(SDG_E_UNSUPPORTED, "sdg_step_keep_half: the context's time scheme is not split-IMEX");
+  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_keep_half needs sdg_set_diffusivity");
+  if (!ctx->state) return fail(SDG_E_STATE, "sdg_step_keep_half needs sdg_set_fields");
+  if (!dev_x_half) return fail(SDG_E_ARG, "sdg_step_keep_half: NULL buffer");
+  if (dev_x_half == ctx->state || dev_x_half == ctx->stage_a || dev_x_half == ctx->stage_b)
+    return fail(SDG_E_ARG, "sdg_step_keep_half: x_half must not be the state or a workspace stage buffer");
+  DeviceGuard g(ctx->device);
+  if ((st = enqueue_imex_step(ctx, ctx->stream, dev_x_half)) != SDG_OK) return st;
   g_err.clear();
   return SDG_OK;
 }
@@ -1212,22 +1231,25 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
   return SDG_OK;
 }
 
-sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_prev,
-                                 double* dev_dkappa) {
-  sdg_status st = check_explicit(ctx, "sdg_step_adjoint_imex");
+namespace {
+// The reverse split-IMEX step; x is the state before the forward step
+// (half = false: x_h is rebuilt from it when dkappa is asked for) or that
+// step's x_h (half = true).
+sdg_status adjoint_imex(sdg_ctx* ctx, const char* who, const void* dev_z_next, void* dev_z_out, const void* dev_x,
+                        bool half, double* dev_dkappa) {
+  sdg_status st = check_explicit(ctx, who);
   if (st != SDG_OK) return st;
-  if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint_imex needs an FP64 context");
-  if (ctx->scheme != SDG_SCHEME_SPLIT_IMEX)
-    return fail(SDG_E_UNSUPPORTED, "sdg_step_adjoint_imex reverses the split-IMEX step only");
-  if (!ctx->kappa) return fail(SDG_E_STATE, "sdg_step_adjoint_imex needs sdg_set_diffusivity");
-  if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "sdg_step_adjoint_imex: NULL buffer");
-  if (dev_z_out == dev_z_next || dev_z_out == dev_x_prev)
-    return fail(SDG_E_ARG, "sdg_step_adjoint_imex: z_out must not alias z_next or x_prev");
-  if (dev_dkappa && !dev_x_prev) return fail(SDG_E_ARG, "sdg_step_adjoint_imex: dkappa needs x_prev");
+  if (ctx->plan.fp32) return fail(SDG_E_UNSUPPORTED, "%s needs an FP64 context", who);
+  if (ctx->scheme != SDG_SCHEME_SPLIT_IMEX) return fail(SDG_E_UNSUPPORTED, "%s reverses the split-IMEX step only", who);
+  if (!ctx->kappa) return fail(SDG_E_STATE, "%s needs sdg_set_diffusivity", who);
+  if (!dev_z_next || !dev_z_out) return fail(SDG_E_ARG, "%s: NULL buffer", who);
+  if (dev_z_out == dev_z_next || dev_z_out == dev_x)
+    return fail(SDG_E_ARG, "%s: z_out must not alias z_next or the forward state", who);
+  if (dev_dkappa && !dev_x) return fail(SDG_E_ARG, "%s: dkappa needs the forward state", who);
   void* A = ctx->stage_a;
   void* B = ctx->stage_b;
-  if (dev_z_out == A || dev_z_out == B || dev_z_next == A || dev_z_next == B || dev_x_prev == A || dev_x_prev == B)
-    return fail(SDG_E_ARG, "sdg_step_adjoint_imex: buffers must not be the workspace stage buffers");
+  if (dev_z_out == A || dev_z_out == B || dev_z_next == A || dev_z_next == B || dev_x == A || dev_x == B)
+    return fail(SDG_E_ARG, "%s: buffers must not be the workspace stage buffers", who);
   DeviceGuard g(ctx->device);
   const Plan& P = ctx->plan;
   hipStream_t s = ctx->stream;
@@ -1245,10 +1267,11 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
   double* mu = static_cast<double*>(A);
   double* w = static_cast<double*>(B);
   hipError_t e = hipSuccess;
-  if (dev_dkappa) {
+  const double* xh = half ? static_cast<const double*>(dev_x) : out;
+  if (dev_dkappa && !half) {
     // x_h of the step being reversed, kept in z_out until the last stage:
     // the half step from x_prev, then its column solve in place
-    StageArgs s1 = stage_args(ctx, nullptr, dev_x_prev, dev_z_out, 0.0, 1.0, h);
+    StageArgs s1 = stage_args(ctx, nullptr, dev_x, dev_z_out, 0.0, 1.0, h);
     e = launch_stage(s1, false, wz, false, false, s);
     if (e == hipSuccess) e = hdiff_after_stage(ctx, s1, h, 0.0, s);
     if (e != hipSuccess) return hip_fail(e, "split-IMEX adjoint half step launch");
@@ -1265,7 +1288,7 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
     e = launch_tsolve(ctx->dm, P.F, w, mu, ctx->kappa, ctx->tfac, h, ctx->eta, false, s);
   }
   if (e == hipSuccess && dev_dkappa)
-    e = launch_kappa_gradient(ctx->dm, P.F, mu, out, ctx->kpart, ctx->eta, h, dev_dkappa, s);
+    e = launch_kappa_gradient(ctx->dm, P.F, mu, xh, ctx->kpart, ctx->eta, h, dev_dkappa, s);
   // Z0 = mu' + h L~ mu' + Z1 - w
   if (e == hipSuccess)
     e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, mu, Z1, w, out, U, h, 1.0, 1.0, -1.0, s);
@@ -1273,6 +1296,17 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
   if (e != hipSuccess) return hip_fail(e, "split-IMEX adjoint launch");
   g_err.clear();
   return SDG_OK;
+}
+}  // namespace
+
+sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_prev,
+                                 double* dev_dkappa) {
+  return adjoint_imex(ctx, "sdg_step_adjoint_imex", dev_z_next, dev_z_out, dev_x_prev, false, dev_dkappa);
+}
+
+sdg_status sdg_step_adjoint_imex_half(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_out, const void* dev_x_half,
+                                      double* dev_dkappa) {
+  return adjoint_imex(ctx, "sdg_step_adjoint_imex_half", dev_z_next, dev_z_out, dev_x_half, true, dev_dkappa);
 }
 
 sdg_status sdg_column_dv_solve(sdg_ctx* ctx, int kind, int n_comp, const void* dev_F, void* dev_x) {

@@ -34,6 +34,7 @@ EXPORTED = (
     "sdg_mass", "sdg_sync", "sdg_get_tuning", "sdg_set_tuning", "sdg_autotune",
     "sdg_graph_capture_step", "sdg_graph_launch", "sdg_apply_mass", "sdg_m_dot", "sdg_step_adjoint",
     "sdg_column_dv_solve", "sdg_step_adjoint_imex", "sdg_mass_noalloc", "sdg_stream_probe",
+    "sdg_step_keep_half", "sdg_step_adjoint_imex_half",
 )
 
 
@@ -135,6 +136,8 @@ def load_library(path: str | None = None):
         "sdg_step_adjoint": ([vp, vp, vp, vp, vp], i32),
         "sdg_column_dv_solve": ([vp, i32, i32, vp, vp], i32),
         "sdg_step_adjoint_imex": ([vp, vp, vp, vp, vp], i32),
+        "sdg_step_keep_half": ([vp, vp], i32),
+        "sdg_step_adjoint_imex_half": ([vp, vp, vp, vp, vp], i32),
         "sdg_mass_noalloc": ([vp, vp, vp], i32),
         "sdg_stream_probe": ([i32, vp, vp, sz, i32, vp], i32),
     }
@@ -393,6 +396,24 @@ class SlimDG:
         _check(self.lib.sdg_step_adjoint_imex(self.ctx, _ptr(z_next), _ptr(z_out),
                                               None if x_prev is None else _ptr(x_prev),
                                               None if dkappa is None else _ptr(dkappa)))
+
+    def step_keep_half(self, x_half):
+        """One split-IMEX step of the set fields that leaves its half-step
+        state x_h in x_half (what step_adjoint_imex_half takes)."""
+        self._check_nodal(x_half, self.n_fields)
+        _check(self.lib.sdg_step_keep_half(self.ctx, _ptr(x_half)))
+
+    def step_adjoint_imex_half(self, z_next, z_out, x_half=None, dkappa=None):
+        """Reverse of one split-IMEX step given that step's x_h."""
+        self._check_nodal(z_next, self.n_fields)
+        self._check_nodal(z_out, self.n_fields)
+        if x_half is not None:
+            self._check_nodal(x_half, self.n_fields)
+        if dkappa is not None and (dkappa.dtype != self.torch.float64 or dkappa.numel() < int(self.layout.max_layers)):
+            raise ValueError("dkappa must be a float64 device tensor with >= max_layers entries")
+        _check(self.lib.sdg_step_adjoint_imex_half(self.ctx, _ptr(z_next), _ptr(z_out),
+                                                   None if x_half is None else _ptr(x_half),
+                                                   None if dkappa is None else _ptr(dkappa)))
 
     def step_adjoint(self, z_next, z_out, x_next=None, dkappa=None):
         self._check_nodal(z_next, self.n_fields)

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(P.EXPORTED)
-    assert lib.sdg_abi_version() == 7
+    assert lib.sdg_abi_version() == 8
 
 
 def test_layout_matches_cell_formula():
