@@ -548,6 +548,8 @@ def main():
                     help="time only the matrix-free column solves and print their JSON")
     ap.add_argument("--hdiff-only", action="store_true",
                     help="time only the horizontal diffusion form and print its JSON")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the adjoint form (gradient over 200 steps) and print its JSON")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device twice (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -579,6 +581,9 @@ def main():
         return
     if args.hdiff_only:
         print(json.dumps({"hdiff_form": hdiff_form(w, 10, torch, P_mod)}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_form": adjoint_form(torch, P_mod, W)}), flush=True)
         return
     copy_gbps = copy_bandwidth(torch)
     log(f"torch device copy: {copy_gbps:.0f} GB/s (read + write)")
