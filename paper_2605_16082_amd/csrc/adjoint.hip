@@ -426,6 +426,9 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
   double* __restrict__ Gsc = a.gfac;
   const double sd = Jh * (1.0 / 12.0), so = Jh * (1.0 / 24.0);
 
+  // Each layer's loads are issued one layer ahead of their use (the next
+  // layer's Z and the geometry two layers down), so that a column's serial
+  // sweep does not wait a memory round trip per layer.
   LayerGeo gc, gn, gp;
   load_layer(m, lt0, gc);
   double kvc[6];
@@ -434,14 +437,32 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
   double yp[kF][6];
   double kp = 0.0;
   gp = gc;
+  double zc[kF][6];
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) zc[f][i] = a.Z[(size_t)(f * 6 + i) * SL + p0];
+  double kn = 0.0;
+  if (N > 1) {
+    load_layer(m, lt0 + (size_t)kCell, gn);
+    kn = kap[1];
+  }
   for (int l = 0; l < N; ++l) {
     const size_t p = p0 + (size_t)l * kCell;
     const double kc = kap[l];
     const bool below = l < N - 1;
-    double kn = 0.0;
+    double zx[kF][6];
     if (below) {
-      load_layer(m, lt0 + (size_t)(l + 1) * kCell, gn);
-      kn = kap[l + 1];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) zx[f][i] = a.Z[(size_t)(f * 6 + i) * SL + p + kCell];
+    }
+    LayerGeo gnn = gn;
+    double knn = 0.0;
+    if (l + 2 < N) {
+      load_layer(m, lt0 + (size_t)(l + 2) * kCell, gnn);
+      knn = kap[l + 2];
     }
     double mz[6];
     mass_z(gc, Jh, mz);
@@ -474,9 +495,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
     double r[kF][6];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      double t[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) t[i] = a.Z[(size_t)(f * 6 + i) * SL + p];
+      const double* t = zc[f];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         double at = 0.0, ab = 0.0;
@@ -593,7 +612,13 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
     if (below) {
       gc = gn;
       vertical_stiffness(gc, Jh, kvc);
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) zc[f][i] = zx[f][i];
     }
+    gn = gnn;
+    kn = knn;
   }
   if (NF == 0) return;
   // back substitution
@@ -608,21 +633,50 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
         a.mu[(size_t)(f * 6 + i) * SL + p] = yp[f][i];
       }
   }
-  for (int l = N - 2; l >= 0; --l) {
-    const size_t p = p0 + (size_t)l * kCell;
-    double G[6][3];
+  // G_l and y_l one layer ahead of their use, as in the forward sweep
+  double G[6][3], yl[kF][6];
+  if (N > 1) {
+    const size_t p = p0 + (size_t)(N - 2) * kCell;
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int q = 0; q < 3; ++q) G[i][q] = Gsc[(size_t)(i * 3 + q) * SL + p];
 #pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int i = 0; i < 6; ++i) yl[f][i] = a.mu[(size_t)(f * 6 + i) * SL + p];
+  }
+  for (int l = N - 2; l >= 0; --l) {
+    const size_t p = p0 + (size_t)l * kCell;
+    double Gx[6][3], yx[kF][6];
+    if (l > 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) Gx[i][q] = Gsc[(size_t)(i * 3 + q) * SL + p - kCell];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) yx[f][i] = a.mu[(size_t)(f * 6 + i) * SL + p - kCell];
+    }
+#pragma unroll
     for (int f = 0; f < NF; ++f) {
       double xt[3] = {xn[f][0], xn[f][1], xn[f][2]};
 #pragma unroll
       for (int i = 0; i < 6; ++i)
-        xn[f][i] = a.mu[(size_t)(f * 6 + i) * SL + p] - (G[i][0] * xt[0] + G[i][1] * xt[1] + G[i][2] * xt[2]);
+        xn[f][i] = yl[f][i] - (G[i][0] * xt[0] + G[i][1] * xt[1] + G[i][2] * xt[2]);
 #pragma unroll
       for (int i = 0; i < 6; ++i) a.mu[(size_t)(f * 6 + i) * SL + p] = xn[f][i];
+    }
+    if (l > 0) {
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) G[i][q] = Gx[i][q];
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) yl[f][i] = yx[f][i];
     }
   }
 }
@@ -635,18 +689,7 @@ __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
 // [v] = v_up,bottom - v_dn,top across a face and S = M_h:
 //   volume of l:                -(mu_t - mu_b)^T Kv_l (x_t - x_b)
 //   each face touching l:       -[mu]^T (s' S [x] + Kv_l (x_l,t - x_l,b) / 2)
-// The 64 columns of a cell are summed with a fixed butterfly, cells per
-// layer with a fixed tree; a layer's g is complete once the face below it
-// has been seen.
 // ---------------------------------------------------------------------------
-struct KGradArgs {
-  DevMesh m;
-  const double* mu;
-  const double* x;
-  double* partial;   // [max_layers][n_cells]
-  double eta;
-};
-
 __device__ __forceinline__ double quad3(const double K[6], const double a[3], const double b[3]) {
   double s = 0.0;
 #pragma unroll
@@ -671,80 +714,91 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One thread per prism over the 2-layer tile table, one wavefront per layer
+// of a cell: each prism evaluates every term of its own g (its volume and
+// both faces touching it; the penalty of a face is evaluated by the prisms on
+// both sides), so no column is walked and the loads of all layers are in
+// flight at once.  The 64 columns of a cell are summed with a fixed
+// butterfly, cells per layer with a fixed tree (kgrad_reduce_kernel).
+struct KGradTileArgs {
+  DevMesh m;
+  const WgTile* tiles;
+  const double* mu;
+  const double* x;
+  double* partial;   // [max_layers][n_cells]
+  double eta;
+};
+
 template <int NF>
-__global__ __launch_bounds__(64) void kgrad_kernel(KGradArgs a) {
+__global__ __launch_bounds__(128) void kgrad_tile_kernel(KGradTileArgs a) {
   const DevMesh& m = a.m;
-  const int cell = blockIdx.x;
-  const int lane = threadIdx.x;
+  const WgTile tile = a.tiles[blockIdx.x];
+  const int lane = threadIdx.x & (kCell - 1);
+  const int l = tile.layer0 + (threadIdx.x >> 6);
+  const int cell = tile.cell;
+  const int depth = (m.cell_base[cell + 1] - m.cell_base[cell]) / kCell;
+  if (l >= depth) return;                      // uniform per wavefront
   const int c = cell * kCell + lane;
   const int N = m.nlay[c];
-  const int depth = (m.cell_base[cell + 1] - m.cell_base[cell]) / kCell;
+  const bool live = l < N;
+  const bool up = live && l > 0, dn = live && l + 1 < N;
   const size_t SL = (size_t)m.n_slots;
-  const size_t p0 = (size_t)m.cell_base[cell] + lane;
-  const size_t lt0 = (size_t)m.cell_lbase[cell] + lane;
-  const double Jh = N > 0 ? m.geo[G_JH * m.n_col_slots + c] : 0.0;
-  const double sd = Jh * (1.0 / 12.0), so = Jh * (1.0 / 24.0);
-  double gpend = 0.0;                        // g of the previous layer, face below not yet added
-  double mbp[NF][3], xbp[NF][3], dxp[NF][3];
-  double kvp[6] = {0, 0, 0, 0, 0, 0};
-  double hp = 1.0;
-  for (int l = 0; l < depth; ++l) {
-    double gdone = 0.0;                      // completed g_{l-1}
-    if (l < N) {
-      const size_t p = p0 + (size_t)l * kCell;
-      LayerGeo g;
-      load_layer(m, lt0 + (size_t)l * kCell, g);
-      double kv[6];
-      vertical_stiffness(g, Jh, kv);
-      const double sp = l > 0 ? a.eta / (2.0 * fmin(hp, g.hbar)) : 0.0;
-      double gl = 0.0;
+  const size_t p = (size_t)m.cell_base[cell] + (size_t)l * kCell + lane;
+  const size_t pu = up ? p - kCell : p, pd = dn ? p + kCell : p;
+  const size_t lt = (size_t)m.cell_lbase[cell] + (size_t)l * kCell + lane;
+  double g = 0.0;
+  if (live) {
+    const double Jh = m.geo[G_JH * m.n_col_slots + c];
+    const double sd = Jh * (1.0 / 12.0), so = Jh * (1.0 / 24.0);
+    LayerGeo gl, gu, gd;
+    load_layer(m, lt, gl);
+    load_layer(m, up ? lt - kCell : lt, gu);
+    load_layer(m, dn ? lt + kCell : lt, gd);
+    double kv[6];
+    vertical_stiffness(gl, Jh, kv);
+    const double spu = up ? a.eta / (2.0 * fmin(gu.hbar, gl.hbar)) : 0.0;
+    const double spd = dn ? a.eta / (2.0 * fmin(gl.hbar, gd.hbar)) : 0.0;
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        double mt[3], mb[3], xt[3], xb[3], dm[3], dx[3];
+    for (int f = 0; f < NF; ++f) {
+      double mt[3], mb[3], xt[3], xb[3], dm[3], dx[3];
+      double mub[3], xub[3], mdt[3], xdt[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          mt[i] = a.mu[(size_t)(f * 6 + i) * SL + p];
-          mb[i] = a.mu[(size_t)(f * 6 + i + 3) * SL + p];
-          xt[i] = a.x[(size_t)(f * 6 + i) * SL + p];
-          xb[i] = a.x[(size_t)(f * 6 + i + 3) * SL + p];
-          dm[i] = mt[i] - mb[i];
-          dx[i] = xt[i] - xb[i];
-        }
-        gl -= quad3(kv, dm, dx);
-        if (l > 0) {
-          double jm[3], jx[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            jm[i] = mbp[f][i] - mt[i];
-            jx[i] = xbp[f][i] - xt[i];
-          }
-          const double pen = quadS(sp * sd, sp * so, jm, jx);
-          gl -= pen + 0.5 * quad3(kv, jm, dx);           // kappa_l below the face
-          gpend -= pen + 0.5 * quad3(kvp, jm, dxp[f]);   // kappa_{l-1} above the face
-        }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          mbp[f][i] = mb[i];
-          xbp[f][i] = xb[i];
-          dxp[f][i] = dx[i];
-        }
+      for (int i = 0; i < 3; ++i) {
+        const size_t rt = (size_t)(f * 6 + i) * SL, rb = (size_t)(f * 6 + i + 3) * SL;
+        mt[i] = a.mu[rt + p];
+        mb[i] = a.mu[rb + p];
+        xt[i] = a.x[rt + p];
+        xb[i] = a.x[rb + p];
+        mub[i] = a.mu[rb + pu];
+        xub[i] = a.x[rb + pu];
+        mdt[i] = a.mu[rt + pd];
+        xdt[i] = a.x[rt + pd];
+        dm[i] = mt[i] - mb[i];
+        dx[i] = xt[i] - xb[i];
       }
-      gdone = gpend;
-      gpend = gl;
+      g -= quad3(kv, dm, dx);
+      if (up) {                                 // the face above: kappa_l below it
+        double jm[3], jx[3];
 #pragma unroll
-      for (int i = 0; i < 6; ++i) kvp[i] = kv[i];
-      hp = g.hbar;
-    } else if (l == N) {
-      gdone = gpend;
-      gpend = 0.0;
-    }
-    if (l > 0) {
-      const double v = wave_sum(gdone);
-      if (lane == 0) a.partial[(size_t)(l - 1) * m.n_cells + cell] = v;
+        for (int i = 0; i < 3; ++i) {
+          jm[i] = mub[i] - mt[i];
+          jx[i] = xub[i] - xt[i];
+        }
+        g -= quadS(spu * sd, spu * so, jm, jx) + 0.5 * quad3(kv, jm, dx);
+      }
+      if (dn) {                                 // the face below: kappa_l above it
+        double jm[3], jx[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          jm[i] = mb[i] - mdt[i];
+          jx[i] = xb[i] - xdt[i];
+        }
+        g -= quadS(spd * sd, spd * so, jm, jx) + 0.5 * quad3(kv, jm, dx);
+      }
     }
   }
-  const double v = wave_sum(N == depth ? gpend : 0.0);
-  if (lane == 0 && depth > 0) a.partial[(size_t)(depth - 1) * m.n_cells + cell] = v;
+  const double v = wave_sum(g);
+  if (lane == 0) a.partial[(size_t)l * m.n_cells + cell] = v;
 }
 
 // dkappa[l] += dt * sum over cells deeper than l of partial[l][cell]
@@ -920,21 +974,23 @@ hipError_t launch_tsolve(const DevMesh& m, int n_fields, const double* Z, double
   return hipGetLastError();
 }
 
-hipError_t launch_kappa_gradient(const DevMesh& m, int n_fields, const double* mu, const double* x,
-                                 double* partial, double eta, double dt, double* dkappa, hipStream_t s) {
+hipError_t launch_kappa_gradient(const DevMesh& m, const WgTile* tiles2, int n_tiles2, int n_fields,
+                                 const double* mu, const double* x, double* partial, double eta, double dt,
+                                 double* dkappa, hipStream_t s) {
   if (m.n_cells == 0) return hipSuccess;
-  KGradArgs a{};
+  KGradTileArgs a{};
   a.m = m;
+  a.tiles = tiles2;
   a.mu = mu;
   a.x = x;
   a.partial = partial;
   a.eta = eta;
-  dim3 grid(m.n_cells), block(kCell);
+  const dim3 grid(n_tiles2), block(2 * kCell);
   switch (n_fields) {
-    case 1: hipLaunchKernelGGL((kgrad_kernel<1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((kgrad_kernel<2>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((kgrad_kernel<3>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((kgrad_kernel<4>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((kgrad_tile_kernel<1>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((kgrad_tile_kernel<2>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((kgrad_tile_kernel<3>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((kgrad_tile_kernel<4>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

@@ -1207,7 +1207,8 @@ sdg_status sdg_step_adjoint(sdg_ctx* ctx, const void* dev_z_next, void* dev_z_ou
                                ctx->tfac, ctx->dt, ctx->eta, false, s);
   if (e != hipSuccess) return hip_fail(e, "transposed solve launch");
   if (dev_dkappa) {
-    e = launch_kappa_gradient(ctx->dm, P.F, mu, static_cast<const double*>(dev_x_next), ctx->kpart, ctx->eta,
+    e = launch_kappa_gradient(ctx->dm, ctx->tiles[1], P.n_tiles[1], P.F, mu, static_cast<const double*>(dev_x_next),
+                              ctx->kpart, ctx->eta,
                               ctx->dt, dev_dkappa, s);
     if (e != hipSuccess) return hip_fail(e, "kappa gradient launch");
   }
@@ -1288,7 +1289,8 @@ sdg_status adjoint_imex(sdg_ctx* ctx, const char* who, const void* dev_z_next, v
     e = launch_tsolve(ctx->dm, P.F, w, mu, ctx->kappa, ctx->tfac, h, ctx->eta, false, s);
   }
   if (e == hipSuccess && dev_dkappa)
-    e = launch_kappa_gradient(ctx->dm, P.F, mu, xh, ctx->kpart, ctx->eta, h, dev_dkappa, s);
+    e = launch_kappa_gradient(ctx->dm, ctx->tiles[1], P.n_tiles[1], P.F, mu, xh, ctx->kpart, ctx->eta, h,
+                              dev_dkappa, s);
   // Z0 = mu' + h L~ mu' + Z1 - w
   if (e == hipSuccess)
     e = launch_adjoint_stage(ctx->dm, tiles, nt, tl, xcd, P.F, wz, mu, Z1, w, out, U, h, 1.0, 1.0, -1.0, s);

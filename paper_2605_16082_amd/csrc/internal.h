@@ -155,8 +155,11 @@ hipError_t launch_adjoint_stage(const DevMesh& m, const WgTile* tiles, int n_til
 // factors (mu may be Z).
 hipError_t launch_tsolve(const DevMesh& m, int n_fields, const double* Z, double* mu, const double* kappa,
                          double* gfac, double dt, double eta, bool factor, hipStream_t s);
-hipError_t launch_kappa_gradient(const DevMesh& m, int n_fields, const double* mu, const double* x,
-                                 double* partial, double eta, double dt, double* dkappa, hipStream_t s);
+// dkappa[l] += dt sum mu^T (dA/dkappa_l) x, one thread per prism over the
+// 2-layer tile table (tiles2, n_tiles2), per-cell sums in partial.
+hipError_t launch_kappa_gradient(const DevMesh& m, const WgTile* tiles2, int n_tiles2, int n_fields,
+                                 const double* mu, const double* x, double* partial, double eta, double dt,
+                                 double* dkappa, hipStream_t s);
 hipError_t launch_mass_apply(const DevMesh& m, const void* X, void* Y, int n_fields, bool fp32, bool inverse,
                              hipStream_t s);
 hipError_t launch_mdot_columns(const DevMesh& m, const void* X, const void* Y, int n_fields, bool fp32,
