@@ -99,17 +99,22 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
     dz[v] = zt[v] - zb[v];
   }
   double res[NF][6];
+  // the prism's own velocity and Y, loaded once and reused by every term
+  double u[6], v[6], w[6], yv[NF][6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    u[i] = ld(U + (size_t)(0 * 6 + i) * S, po);
+    v[i] = ld(U + (size_t)(1 * 6 + i) * S, po);
+    w[i] = WZ ? 0.0 : ld(U + (size_t)(2 * 6 + i) * S, po);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+#pragma unroll
+    for (int i = 0; i < 6; ++i) yv[f][i] = ld(Y + (size_t)(f * 6 + i) * S, po);
 
   // ---- volume: int phi_j U.grad(y_h) ----
   {
     double hx[2][3], he[2][3], G[2][6];
-    double u[6], v[6], w[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      u[i] = ld(U + (size_t)(0 * 6 + i) * S, po);
-      v[i] = ld(U + (size_t)(1 * 6 + i) * S, po);
-      w[i] = WZ ? 0.0 : ld(U + (size_t)(2 * 6 + i) * S, po);
-    }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
       const double tk = kZt[k], bk = kZb[k];
@@ -153,9 +158,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      double y[6];
-#pragma unroll
-      for (int i = 0; i < 6; ++i) y[i] = ld(Y + (size_t)(f * 6 + i) * S, po);
+      const double* y = yv[f];
       const double d0 = y[0] - y[3], d1 = y[1] - y[4], d2 = y[2] - y[5];
 #pragma unroll
       for (int i = 0; i < 6; ++i) res[f][i] = 0.0;
@@ -193,10 +196,10 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
     if (interior && l >= (meta >> 2)) continue;  // wall
     const double nx = ld(geo + (G_NX + e) * CS, co), ny = ld(geo + (G_NY + e) * CS, co);
     const double Le = ld(geo + (G_LE + e) * CS, co);
-    const uint32_t oi[4] = {A * rs + po, B * rs + po, (A + 3) * rs + po, (B + 3) * rs + po};
+    const int oi[4] = {A, B, A + 3, B + 3};      // the face's own nodes
     double un[4];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) un[n] = nx * ld(U, oi[n]) + ny * ld(U + 6 * S, oi[n]);
+    for (int n = 0; n < 4; ++n) un[n] = nx * u[oi[n]] + ny * v[oi[n]];
     uint32_t no[4] = {0, 0, 0, 0};
     if (interior) {
       const int kp = meta & 3;
@@ -242,7 +245,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
       const double* fb = Y + (size_t)(f * 6) * S;
       double d[4];
 #pragma unroll
-      for (int n = 0; n < 4; ++n) d[n] = ld(fb, oi[n]) - (interior ? ld(fb, no[n]) : 0.0);
+      for (int n = 0; n < 4; ++n) d[n] = yv[f][oi[n]] - (interior ? ld(fb, no[n]) : 0.0);
       res[f][A] -= Kp[0][0] * d[0] + Kp[1][0] * d[1] + Kp[0][1] * d[2] + Kp[1][1] * d[3];
       res[f][B] -= Kp[1][0] * d[0] + Kp[2][0] * d[1] + Kp[1][1] * d[2] + Kp[2][1] * d[3];
       res[f][A + 3] -= Kp[0][1] * d[0] + Kp[1][1] * d[1] + Kp[0][2] * d[2] + Kp[1][2] * d[3];
@@ -265,9 +268,8 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
     double un[3];
 #pragma unroll
     for (int n = 0; n < 3; ++n) {
-      const size_t ro = (size_t)(o + n) * S;
-      double val = -(ld(U + ro, po) * jzx + ld(U + 6 * S + ro, po) * jzy);
-      if (!WZ) val += Jh * ld(U + 12 * S + ro, po);
+      double val = -(u[o + n] * jzx + v[o + n] * jzy);
+      if (!WZ) val += Jh * w[o + n];
       un[n] = val;
     }
     if (has_nb) {
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
       double d[3];
 #pragma unroll
       for (int n = 0; n < 3; ++n)
-        d[n] = ld(Y + (size_t)(f * 6 + o + n) * S, po) - (has_nb ? ld(Y + (size_t)(f * 6 + oo + n) * S, pno) : 0.0);
+        d[n] = yv[f][o + n] - (has_nb ? ld(Y + (size_t)(f * 6 + oo + n) * S, pno) : 0.0);
       res[f][o] -= Kp[0] * d[0] + Kp[3] * d[1] + Kp[4] * d[2];
       res[f][o + 1] -= Kp[3] * d[0] + Kp[1] * d[1] + Kp[5] * d[2];
       res[f][o + 2] -= Kp[4] * d[0] + Kp[5] * d[1] + Kp[2] * d[2];
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(256) void adj_stage_kernel(AdjStageArgs a) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       const size_t row = (size_t)(f * 6 + i) * S;
-      double o = a.b * (ld(Y + row, po) + a.dt * L[i]);
+      double o = a.b * (yv[f][i] + a.dt * L[i]);
       if (a.X1) o += a.a1 * ld(a.X1 + row, po);
       if (a.X2) o += a.a2 * ld(a.X2 + row, po);
       st(a.out + row, po, o);
