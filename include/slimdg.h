@@ -384,7 +384,8 @@ sdg_status sdg_step_adjoint_imex(sdg_ctx* ctx, const void* dev_z_next, void* dev
  * is left in dev_x_half ([n_fields][6][n_slots] in the state precision)
  * rather than in the workspace: the state the reverse step pairs with the
  * kappa gradient.  dev_x_half must not be the set fields (SDG_E_ARG).
- * Enqueued on the context stream; does not synchronise. */
+ * Enqueued on the context stream; does not synchronise (and, unlike
+ * sdg_step, never runs the check_finite test). */
 sdg_status sdg_step_keep_half(sdg_ctx* ctx, void* dev_x_half);
 
 /* sdg_step_adjoint_imex given the reversed step's x_h (as left by
