@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -46,12 +47,16 @@ struct Plan {
   int64_t n_prisms = 0, n_slots = 0, n_lslots = 0;
   std::vector<int32_t> cell_base, cell_lbase, cell_depth, member_off;
   std::vector<int64_t> zoff;  // per column: first row of its levels in desc.zlev
+  // per cell, the lateral faces whose neighbour is in another cell
+  // (the horizontal diffusion stages their values in LDS): offsets, largest count
+  std::vector<int32_t> halo_off;
+  int halo_max = 0;
   int n_tiles[kTileChoices] = {};
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_tiles_bucket, o_stage_a, o_stage_b, o_scratch,
       o_tfac,
-      o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, total;
+      o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, o_hoff, o_hslot, o_hdepth, o_hidx, total;
   size_t state_bytes, velocity_bytes;
 };
 
@@ -159,6 +164,17 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   }
   P.cell_base[P.n_cells] = (int32_t)sb;
   P.cell_lbase[P.n_cells] = (int32_t)lb;
+  P.halo_off.assign(P.n_cells + 1, 0);
+  for (int c = 0; c < C; ++c)
+    for (int e = 0; e < 3; ++e) {
+      const int c2 = d->nbr[3 * c + e];
+      if (c2 >= 0 && c2 / kCell != c / kCell) ++P.halo_off[c / kCell + 1];
+    }
+  P.halo_max = 0;
+  for (int k = 0; k < P.n_cells; ++k) {
+    P.halo_max = std::max(P.halo_max, P.halo_off[k + 1]);
+    P.halo_off[k + 1] += P.halo_off[k];
+  }
   P.n_slots = sb;
   P.n_lslots = lb;
   // kernels address a field's 6 node rows (and the velocity's) with 32-bit
@@ -199,6 +215,10 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_kpart = take(sizeof(double) * (size_t)P.max_layers * (size_t)P.n_cells);
   P.o_kh = take(sizeof(double) * (size_t)P.CS);
   P.o_hface = take(sizeof(double) * 15 * (size_t)P.CS);
+  P.o_hoff = take(sizeof(int32_t) * (P.n_cells + 1));
+  P.o_hslot = take(sizeof(int32_t) * std::max<size_t>(P.halo_off[P.n_cells], 1));
+  P.o_hdepth = take(sizeof(int32_t) * std::max<size_t>(P.halo_off[P.n_cells], 1));
+  P.o_hidx = take(sizeof(int32_t) * 3 * (size_t)P.CS);
   P.total = o;
   return SDG_OK;
 }
@@ -433,6 +453,32 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   }
   for (int m = 0; m < P.n_members; ++m)
     for (int c = P.member_off[m]; c < P.member_off[m + 1]; ++c) colmem[c] = m;
+  // other-cell neighbours per cell, column by column, faces in order
+  const size_t n_halo = (size_t)P.halo_off[P.n_cells];
+  std::vector<int32_t> hslot(std::max<size_t>(n_halo, 1), 0), hdepth(std::max<size_t>(n_halo, 1), 0),
+      hidx(3 * (size_t)CS, -1);
+  {
+    // each cell's list sorted by the neighbour's slot (then column and face),
+    // so that consecutive entries read nearby addresses
+    std::vector<std::array<int32_t, 3>> ent;   // (neighbour slot, column, face)
+    for (int k = 0; k < P.n_cells; ++k) {
+      ent.clear();
+      for (int c = k * kCell; c < std::min(C, (k + 1) * kCell); ++c)
+        for (int e = 0; e < 3; ++e) {
+          const int c2 = mesh->nbr[3 * c + e];
+          if (c2 < 0 || c2 / kCell == k) continue;
+          ent.push_back({P.cell_base[c2 / kCell] + c2 % kCell, c, e});
+        }
+      std::sort(ent.begin(), ent.end());
+      for (size_t i = 0; i < ent.size(); ++i) {
+        const int j = P.halo_off[k] + (int)i;
+        const int c = ent[i][1], e = ent[i][2], c2 = mesh->nbr[3 * c + e];
+        hslot[j] = ent[i][0];
+        hdepth[j] = mesh->nlayers[c2];
+        hidx[e * (size_t)CS + c] = (int32_t)i;
+      }
+    }
+  }
   for (int c = 0; c < C; ++c) {
     const int k = c / kCell, lane = c % kCell;
     const int n = mesh->nlayers[c];
@@ -479,6 +525,10 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
       {P.o_tiles[4], tiles[4].data(), sizeof(WgTile) * tiles[4].size()},
       {P.o_tiles[5], tiles[5].data(), sizeof(WgTile) * tiles[5].size()},
       {P.o_tiles[6], tiles[6].data(), sizeof(WgTile) * tiles[6].size()},
+      {P.o_hoff, P.halo_off.data(), sizeof(int32_t) * P.halo_off.size()},
+      {P.o_hslot, hslot.data(), sizeof(int32_t) * hslot.size()},
+      {P.o_hdepth, hdepth.data(), sizeof(int32_t) * hdepth.size()},
+      {P.o_hidx, hidx.data(), sizeof(int32_t) * hidx.size()},
   };
   static_assert(kTileChoices == 7, "one copy per tile table");
   for (const Cp& cp : cps) {
@@ -499,6 +549,11 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   dm.nbr_slot = reinterpret_cast<const int32_t*>(ws + P.o_nbr_slot);
   dm.nbr_meta = reinterpret_cast<const int32_t*>(ws + P.o_nbr_meta);
   dm.nbr_col = reinterpret_cast<const int32_t*>(ws + P.o_nbr_col);
+  dm.halo_max = P.halo_max;
+  dm.halo_off = reinterpret_cast<const int32_t*>(ws + P.o_hoff);
+  dm.halo_slot = reinterpret_cast<const int32_t*>(ws + P.o_hslot);
+  dm.halo_depth = reinterpret_cast<const int32_t*>(ws + P.o_hdepth);
+  dm.halo_idx = reinterpret_cast<const int32_t*>(ws + P.o_hidx);
   dm.geo = reinterpret_cast<const double*>(ws + P.o_geo);
   dm.geo32 = reinterpret_cast<const float*>(ws + P.o_geo32);
   dm.zl = reinterpret_cast<const double*>(ws + P.o_zl);

@@ -98,13 +98,26 @@ struct HFace {
   bool interior;
   int nslot, depth, nA, nB;  // neighbour layer-0 slot, depth, its nodes at the edge ends A and B
   int nlane;                 // neighbour lane when it is in the same cell, else -1
+  int hidx;                  // else its place in the cell's list of other-cell faces
   R Le, sig, khn;            // edge length, penalty, neighbour kh
   R dn[3], dnn[3];           // n . grad(lambda) of the own and the neighbour's basis
 };
 
 constexpr int kHdiffLayers = 2;   // layers per workgroup (the 2-layer tile table)
 
-template <typename R, int NF, bool OUT2>
+// With HALO, the values of the neighbours in other cells are staged in LDS
+// by the whole workgroup, one field ahead of its use: each thread loads a
+// few of the tile's (face, layer, node) items of the next field while the
+// current field computes, stores them after it, and one barrier per field
+// publishes them.  A thread's own other-cell gathers, one round per field
+// that nothing else could overlap at two wavefronts per SIMD, took a third
+// of the kernel's time.  Cells with more than kHaloCap such faces (none on a
+// locality-ordered mesh of 64-column cells) take the kernel without HALO,
+// which gathers them per thread.
+constexpr int kHaloCap = 64;
+constexpr int kHaloItems = (kHaloCap * kHdiffLayers * 6 + kCell * kHdiffLayers - 1) / (kCell * kHdiffLayers);
+
+template <typename R, int NF, bool OUT2, bool HALO>
 __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a) {
   const DevMesh& m = a.m;
   const WgTile tile = a.tiles[blockIdx.x];
@@ -117,6 +130,8 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
   // the tile's stage input, [row][layer][lane]: neighbours in the same cell
   // are read from here
   __shared__ R sh[6 * NF][kHdiffLayers][kCell];
+  // other-cell neighbours of one field, double-buffered: [buffer][face][layer][node]
+  __shared__ R hb[HALO ? 2 : 1][HALO ? kHaloCap : 1][kHdiffLayers][6];
   const int li = threadIdx.x / kCell;
   const bool live = l < m.nlay[c];
   const int64_t p = (int64_t)m.cell_base[cell] + lane + (int64_t)l * kCell;
@@ -144,6 +159,7 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
     F.interior = F.nslot >= 0;
     const uint32_t nl_ = (uint32_t)F.nslot - cbase;
     F.nlane = (F.interior && nl_ < (uint32_t)kCell) ? (int)nl_ : -1;
+    F.hidx = HALO ? m.halo_idx[e * CS + c] : -1;
     const int meta = m.nbr_meta[e * CS + c];
     F.depth = F.interior ? (meta >> 2) : 0;
     const int kp = meta & 3;
@@ -158,6 +174,33 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
     for (int j = 0; j < 3; ++j) F.dnn[j] = R(hfe[(size_t)(2 + j) * CS]);
   }
 
+  // this thread's halo items: item it = (face j, layer lj, node i), read
+  // from the neighbour's slot at the tile's layer when the neighbour has it
+  uint32_t hsrc[HALO ? kHaloItems : 1];
+  int hdst[HALO ? kHaloItems : 1];
+  R hv[HALO ? kHaloItems : 1];
+  if constexpr (HALO) {
+    const int hbase = m.halo_off[cell];
+    const int hn = m.halo_off[cell + 1] - hbase;
+#pragma unroll
+    for (int k = 0; k < kHaloItems; ++k) {
+      // consecutive threads take consecutive faces of the list (sorted by the
+      // neighbour's slot) for one (node, layer), so neighbouring lanes read
+      // nearby addresses of one row
+      const int it = (int)threadIdx.x + k * kCell * kHdiffLayers;
+      const int j = it % kHaloCap, lj = (it / kHaloCap) % kHdiffLayers, i = it / (kHaloCap * kHdiffLayers);
+      const int ll = tile.layer0 + lj;
+      // list index in bounds for every thread (entry 0 exists), used only when valid
+      const int e = j < hn ? hbase + j : 0;
+      const int nslot = m.halo_slot[e], ndepth = m.halo_depth[e];
+      const bool ok = j < hn && lj < (int)tile.nlay && ll < ndepth;
+      hdst[k] = ok ? (j * kHdiffLayers + lj) * 6 + i : -1;
+      // an invalid item reads offset 0 (in bounds) and is never stored
+      hsrc[k] = ok ? ((uint32_t)i * (uint32_t)S + (uint32_t)nslot + (uint32_t)ll * kCell) * (uint32_t)sizeof(R) : 0u;
+      hv[k] = *reinterpret_cast<const R*>(reinterpret_cast<const char*>(Ts) + hsrc[k]);
+    }
+  }
+
   const int64_t lt = (int64_t)m.cell_lbase[cell] + lane + (int64_t)l * kCell;
   R dz[3] = {R(0), R(0), R(0)};
   if (live) {
@@ -166,8 +209,13 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
 #pragma unroll
     for (int r = 0; r < 6 * NF; ++r) sh[r][li][lane] = Ts[(size_t)r * S + (size_t)p];
   }
+  if constexpr (HALO) {
+#pragma unroll
+    for (int k = 0; k < kHaloItems; ++k)
+      if (hdst[k] >= 0) (&hb[0][0][0][0])[hdst[k]] = hv[k];
+  }
   __syncthreads();
-  if (!live) return;
+  if (!HALO && !live) return;
   {
     // volume factor kh int_K z_zeta J_h dxi deta = kh J_h (dz_0 + dz_1 + dz_2) / 12
     const R vf = kh * Jh * (dz[0] + dz[1] + dz[2]) * R(1.0 / 12.0);
@@ -182,6 +230,16 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       const R* Tf = Ts + (size_t)(f * 6) * S;
+      // the next field's halo items, stored after this field's arithmetic
+      if constexpr (HALO) {
+        if (f + 1 < NF) {
+          const char* nb = reinterpret_cast<const char*>(Ts + (size_t)((f + 1) * 6) * S);
+#pragma unroll
+          for (int k = 0; k < kHaloItems; ++k) hv[k] = *reinterpret_cast<const R*>(nb + hsrc[k]);
+        }
+      }
+      if (HALO && !live) goto next_field;
+      {
       // the field's current output values, loaded before its arithmetic
       R o[6], o2[6];
 #pragma unroll
@@ -217,6 +275,9 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
         if (F.nlane >= 0) {
 #pragma unroll
           for (int i = 0; i < 6; ++i) Tn[i] = sh[f * 6 + i][li][F.nlane];
+        } else if constexpr (HALO) {
+#pragma unroll
+          for (int i = 0; i < 6; ++i) Tn[i] = hb[f & 1][F.hidx][li][i];
         } else {
 #pragma unroll
           for (int i = 0; i < 6; ++i) Tn[i] = Tf[(size_t)i * S + q];
@@ -276,21 +337,36 @@ __global__ __launch_bounds__(kCell * kHdiffLayers) void hdiff_kernel(HdiffArgs a
         Out[oi] = o[i] + c1 * L[i];
         if (OUT2) Out2[oi] = o2[i] + c2 * L[i];
       }
+      }
+    next_field:
+      if constexpr (HALO) {
+        if (f + 1 < NF) {
+#pragma unroll
+          for (int k = 0; k < kHaloItems; ++k)
+            if (hdst[k] >= 0) (&hb[(f + 1) & 1][0][0][0])[hdst[k]] = hv[k];
+          __syncthreads();
+        }
+      }
     }
   }
 }
 
-template <typename R, bool OUT2>
-hipError_t launch_nf(const HdiffArgs& a, hipStream_t s) {
+template <typename R, bool OUT2, bool HALO>
+hipError_t launch_halo(const HdiffArgs& a, hipStream_t s) {
   const dim3 grid(a.n_tiles), block(kCell * kHdiffLayers);
   switch (a.n_fields) {
-    case 1: hipLaunchKernelGGL((hdiff_kernel<R, 1, OUT2>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((hdiff_kernel<R, 2, OUT2>), grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((hdiff_kernel<R, 3, OUT2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((hdiff_kernel<R, 4, OUT2>), grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((hdiff_kernel<R, 1, OUT2, HALO>), grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((hdiff_kernel<R, 2, OUT2, HALO>), grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((hdiff_kernel<R, 3, OUT2, HALO>), grid, block, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((hdiff_kernel<R, 4, OUT2, HALO>), grid, block, 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename R, bool OUT2>
+hipError_t launch_nf(const HdiffArgs& a, hipStream_t s) {
+  return a.m.halo_max <= kHaloCap ? launch_halo<R, OUT2, true>(a, s) : launch_halo<R, OUT2, false>(a, s);
 }
 
 }  // namespace

@@ -46,6 +46,16 @@ struct DevMesh {
   const float* zl32;           // same, float
   const double* xy;            // [6][n_col_slots] x0,y0,x1,y1,x2,y2 (input of the geometry kernel)
   const int32_t* col_member;   // [n_col_slots] member id (-1 on padding)
+  // lateral faces whose neighbour is in another cell, listed per cell
+  // (column by column, faces in order): the list of cell k is
+  // halo_off[k] .. halo_off[k + 1] - 1, with the neighbour's layer-0 slot and
+  // depth; halo_idx[e][c] is face e of column c's place in its cell's list,
+  // or -1.  halo_max: the longest list.
+  int32_t halo_max;
+  const int32_t* halo_off;     // [n_cells + 1]
+  const int32_t* halo_slot;
+  const int32_t* halo_depth;
+  const int32_t* halo_idx;     // [3][n_col_slots]
 };
 
 // A workgroup of the per-prism kernels covers tile_layers consecutive layers

@@ -44,6 +44,56 @@ def test_pure_diffusion_operator(name):
     assert np.all(err <= TOL64), err
 
 
+def _shuffled_columns(w, seed=4):
+    """The workload with its triangles in random order: a 64-column cell then
+    has most of its lateral faces on neighbours in other cells."""
+    C = len(w.tri)
+    perm = np.random.default_rng(seed).permutation(C)
+    inv = np.empty(C, dtype=np.int64)
+    inv[perm] = np.arange(C)
+    nbr = np.where(w.nbr[perm] >= 0, inv[np.maximum(w.nbr[perm], 0)], -1).astype(w.nbr.dtype)
+    zoff = np.concatenate([[0], np.cumsum(w.nlayers + 1)])
+    poff = np.concatenate([[0], np.cumsum(w.nlayers)])
+    zlev = np.concatenate([w.zlev[zoff[c]:zoff[c + 1]] for c in perm])
+    pr = np.concatenate([np.arange(poff[c], poff[c + 1]) for c in perm])
+    return W.Workload(w.name + "_shuffled", w.vxy, w.tri[perm], nbr, w.nlayers[perm], zlev, w.U[:, :, pr],
+                      w.T0[:, :, pr], w.kappa, w.dt, w.t_ext, penalty=w.penalty, w_is_zero=w.w_is_zero)
+
+
+def _most_other_cell_faces_per_cell(w):
+    C = len(w.tri)
+    cell = np.arange(C) // 64
+    cross = (w.nbr >= 0) & ((w.nbr // 64) != cell[:, None])
+    return int(np.bincount(cell, weights=cross.sum(axis=1)).max())
+
+
+@pytest.mark.parametrize("shuffled", [False, True])
+def test_other_cell_neighbours_staged_or_gathered(shuffled):
+    """In locality order a cell has at most a few dozen faces on other cells,
+    whose values the kernel stages in LDS (64 at most); in random order it has
+    far more, and the kernel gathers them per thread instead.  Both against
+    the oracle, with advection and three steps."""
+    w0, _ = case("rotating_blob")
+    w = _shuffled_columns(w0) if shuffled else w0
+    most = _most_other_cell_faces_per_cell(w)
+    assert (most > 64) == shuffled, most
+    m = O.PrismMesh(w.vxy, w.tri, w.nbr, w.nlayers, w.zlev)
+    s, U, kappa, state = upload(w)
+    kh = okubo_diffusivity(m, SCALE)
+    L = s.rhs_3d(state)
+    s.sync()
+    ref = O.explicit_operator(m, w.U, w.T0, w.t_ext, kappa_h=kh, eta=w.penalty)
+    err = rel_err(s.gather(L), ref)
+    s.step(3)
+    s.sync()
+    x = w.T0
+    for _ in range(3):
+        x = O.step(m, w.U, w.kappa, x, w.dt, w.t_ext, w.penalty, kappa_h=kh)
+    err3 = rel_err(s.gather(state), x)
+    print("shuffled" if shuffled else "locality order", most, "faces on other cells at most;", err, err3)
+    assert np.all(err <= TOL64) and np.all(err3 <= TOL64), (err, err3)
+
+
 @pytest.mark.parametrize("name", ["rotating_blob", "ragged", "wnonzero"])
 def test_rhs_and_stages_with_advection(name):
     w, m = case(name)
