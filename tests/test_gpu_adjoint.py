@@ -132,6 +132,29 @@ def test_adjoint_long_horizon_matches_oracle():
     assert_kappa_gradient(gk, dk[:, 1], dk[:, 2])
 
 
+def test_adjoint_blob_gradient_matches_oracle():
+    """The differentiation configuration in full (49,928 triangles x 20
+    layers, 998,560 prisms; 200 steps, a checkpoint every 20): the GPU
+    gradient against the oracle's, stored by
+    tests/golden/make_adjoint_blob_reference.py (J; dJ/dkappa per layer with
+    its magnitude sums; dJ/dT0 through its maximum, its 2-norm and 20,064
+    sampled entries)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "adjoint_blob_200steps.npz"))
+    w = W.adjoint_blob()
+    J, gT, gk, s = _gpu_gradient(w, int(g["steps"]), 20)
+    gT = gT[0].ravel()
+    e_s = np.abs(gT[g["idx"]] - g["vals"]).max() / float(g["dT0_max"])
+    print("J", J, float(g["J"]), "dT0 sampled", e_s, "max", np.abs(gT).max() / float(g["dT0_max"]) - 1,
+          "norm", np.sqrt(np.sum(gT * gT)) / float(g["dT0_norm2"]) - 1,
+          "dkappa / term magnitudes", (np.abs(gk[:len(g["dkappa"])] - g["dkappa"]) / g["dkappa_abs"]).max())
+    assert abs(J - float(g["J"])) <= 1e-12 * float(g["J"])
+    assert e_s <= 1e-12
+    assert abs(np.abs(gT).max() - float(g["dT0_max"])) <= 1e-12 * float(g["dT0_max"])
+    assert abs(np.sqrt(np.sum(gT * gT)) - float(g["dT0_norm2"])) <= 1e-12 * float(g["dT0_norm2"])
+    assert_kappa_gradient(gk[:len(g["dkappa"])], g["dkappa"], g["dkappa_abs"])
+
+
 def test_checkpoint_interval_does_not_change_gradient():
     w, m = _case("ragged")
     ref = None
@@ -254,6 +277,44 @@ def test_imex_adjoint_matches_oracle(name, okubo):
     assert abs(J - Jr) <= 1e-12 * abs(Jr)
     assert rel(gT, gTr) <= 1e-12
     assert_kappa_gradient(gk, gkr, gka)
+
+
+@pytest.mark.parametrize("okubo", [0.0, 50.0])
+def test_imex_reverse_step_from_kept_half_state(okubo):
+    """sdg_step_keep_half + sdg_step_adjoint_imex_half (x_h kept by the
+    forward step) give bitwise what sdg_step + sdg_step_adjoint_imex (x_h
+    rebuilt from the state before the step) give, over three steps; the kept
+    step advances the state exactly as sdg_step does."""
+    import torch
+    w, m = _case("ragged")
+    s, U, kappa, state = P.from_workload(w, time_scheme=P.SDG_SCHEME_SPLIT_IMEX, okubo_scale=okubo)
+    x0 = state.clone()
+    xs_prev, xs_half = [], []
+    for _ in range(3):
+        xs_prev.append(state.clone())
+        s.step(1)
+    after = state.clone()
+    state.copy_(x0)
+    for _ in range(3):
+        xh = s.new_state()
+        s.step_keep_half(xh)
+        xs_half.append(xh)
+    assert torch.equal(state, after)
+    rng = np.random.default_rng(11)
+    z1 = s.scatter(rng.standard_normal(w.T0.shape))
+    z2 = z1.clone()
+    dk1 = torch.zeros(64, dtype=torch.float64, device=s.device)
+    dk2 = torch.zeros_like(dk1)
+    for j in range(2, -1, -1):
+        zn = s.new_state()
+        s.step_adjoint_imex(z1, zn, xs_prev[j], dk1)
+        z1 = zn
+        zn = s.new_state()
+        s.step_adjoint_imex_half(z2, zn, xs_half[j], dk2)
+        z2 = zn
+    assert torch.equal(z1, z2) and torch.equal(dk1, dk2)
+    with pytest.raises(P.SlimDGError):
+        s.step_keep_half(state)              # the set fields themselves
 
 
 def test_imex_checkpoint_interval_does_not_change_gradient():
