@@ -414,7 +414,7 @@ template <int NF>
 __global__ __launch_bounds__(64) void tsolve_kernel(TSolveArgs a) {
   constexpr int kF = NF > 0 ? NF : 1;   // array extent (the factor sweep has no fields)
   const DevMesh& m = a.m;
-  const int cell = xcd_tile(blockIdx.x, m.n_cells);
+  const int cell = m.cell_order[blockIdx.x];   // deepest cells first
   const int lane = threadIdx.x;
   const int c = cell * kCell + lane;
   const int N = m.nlay[c];

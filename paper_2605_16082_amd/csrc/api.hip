@@ -51,12 +51,14 @@ struct Plan {
   // (the horizontal diffusion stages their values in LDS): offsets, largest count
   std::vector<int32_t> halo_off;
   int halo_max = 0;
+  // cells deepest first (stable): the dispatch order of the column solves
+  std::vector<int32_t> cell_order;
   int n_tiles[kTileChoices] = {};
   // workspace offsets (bytes)
   size_t o_cell_base, o_cell_lbase, o_nlay, o_nbr_slot, o_nbr_meta, o_nbr_col, o_col_member, o_member_off,
       o_geo, o_geo32, o_xy, o_zl, o_zl32, o_tiles[kTileChoices], o_tiles_bucket, o_stage_a, o_stage_b, o_scratch,
       o_tfac,
-      o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, o_hoff, o_hslot, o_hdepth, o_hidx, total;
+      o_colmass, o_msum, o_flag, o_kpart, o_kh, o_hface, o_hoff, o_hslot, o_hdepth, o_hidx, o_corder, total;
   size_t state_bytes, velocity_bytes;
 };
 
@@ -170,6 +172,10 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
       const int c2 = d->nbr[3 * c + e];
       if (c2 >= 0 && c2 / kCell != c / kCell) ++P.halo_off[c / kCell + 1];
     }
+  P.cell_order.resize(P.n_cells);
+  for (int k = 0; k < P.n_cells; ++k) P.cell_order[k] = k;
+  std::stable_sort(P.cell_order.begin(), P.cell_order.end(),
+                   [&](int32_t x, int32_t y) { return P.cell_depth[x] > P.cell_depth[y]; });
   P.halo_max = 0;
   for (int k = 0; k < P.n_cells; ++k) {
     P.halo_max = std::max(P.halo_max, P.halo_off[k + 1]);
@@ -219,6 +225,7 @@ sdg_status plan_mesh(const sdg_mesh_desc* d, Plan& P) {
   P.o_hslot = take(sizeof(int32_t) * std::max<size_t>(P.halo_off[P.n_cells], 1));
   P.o_hdepth = take(sizeof(int32_t) * std::max<size_t>(P.halo_off[P.n_cells], 1));
   P.o_hidx = take(sizeof(int32_t) * 3 * (size_t)P.CS);
+  P.o_corder = take(sizeof(int32_t) * (size_t)P.n_cells);
   P.total = o;
   return SDG_OK;
 }
@@ -529,6 +536,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
       {P.o_hslot, hslot.data(), sizeof(int32_t) * hslot.size()},
       {P.o_hdepth, hdepth.data(), sizeof(int32_t) * hdepth.size()},
       {P.o_hidx, hidx.data(), sizeof(int32_t) * hidx.size()},
+      {P.o_corder, P.cell_order.data(), sizeof(int32_t) * P.cell_order.size()},
   };
   static_assert(kTileChoices == 7, "one copy per tile table");
   for (const Cp& cp : cps) {
@@ -554,6 +562,7 @@ sdg_status sdg_mesh_upload(sdg_ctx* ctx, const sdg_mesh_desc* mesh, void* dev_wo
   dm.halo_slot = reinterpret_cast<const int32_t*>(ws + P.o_hslot);
   dm.halo_depth = reinterpret_cast<const int32_t*>(ws + P.o_hdepth);
   dm.halo_idx = reinterpret_cast<const int32_t*>(ws + P.o_hidx);
+  dm.cell_order = reinterpret_cast<const int32_t*>(ws + P.o_corder);
   dm.geo = reinterpret_cast<const double*>(ws + P.o_geo);
   dm.geo32 = reinterpret_cast<const float*>(ws + P.o_geo32);
   dm.zl = reinterpret_cast<const double*>(ws + P.o_zl);

@@ -56,6 +56,9 @@ struct DevMesh {
   const int32_t* halo_slot;
   const int32_t* halo_depth;
   const int32_t* halo_idx;     // [3][n_col_slots]
+  // the cells deepest first: the column solves take their cells in this
+  // order, so the longest columns do not end the launch alone
+  const int32_t* cell_order;   // [n_cells]
 };
 
 // A workgroup of the per-prism kernels covers tile_layers consecutive layers

@@ -124,7 +124,7 @@ __device__ __forceinline__ C penalty(C eta, C ka, C kb, C ha, C hb) {
 template <typename S, typename C, int NF>
 __global__ __launch_bounds__(64) void vsolve_kernel(SolveArgs a) {
   const DevMesh& m = a.m;
-  const int cell = xcd_tile(blockIdx.x, m.n_cells);
+  const int cell = m.cell_order[blockIdx.x];   // deepest cells first
   const int lane = threadIdx.x;
   const int c = cell * kCell + lane;
   const int N = m.nlay[c];
