@@ -104,8 +104,26 @@ def build(verbose: bool = False, jobs: int = 8, extra=(), out: str = LIB, objdir
     return out
 
 
+C_EXAMPLE_SRC = os.path.join(ROOT, "tests", "c_abi", "c_abi_step.cpp")
+C_EXAMPLE = os.path.join(ROOT, "tests", "c_abi", "c_abi_step")
+
+
+def build_c_example(verbose: bool = False) -> str:
+    """Compile the C-ABI example program (host code only) against the built
+    library; it finds libslimdg.so through its run path."""
+    tmp = C_EXAMPLE + ".tmp"
+    cmd = [_hipcc(), "-O2", "-std=c++17", "-I", INCLUDE, C_EXAMPLE_SRC, "-L", PKG, "-lslimdg",
+           "-Wl,-rpath,$ORIGIN/../../paper_2605_16082_amd", "-o", tmp]
+    _run(cmd)
+    os.replace(tmp, C_EXAMPLE)
+    if verbose:
+        print("built", C_EXAMPLE, flush=True)
+    return C_EXAMPLE
+
+
 if __name__ == "__main__":
     if "--sanitize" in sys.argv:
         build_sanitized(verbose="-v" in sys.argv)
     else:
         build(verbose="-v" in sys.argv)
+        build_c_example(verbose="-v" in sys.argv)
