@@ -123,3 +123,20 @@ def test_error_message_is_set():
     with pytest.raises(P.SlimDGError) as e:
         P.Mesh(w.vxy, tri, w.nbr, w.nlayers, w.zlev, 1).layout()
     assert "counter-clockwise" in e.value.message
+
+
+def test_layer_count_limits():
+    """A column may hold 1 to 65,535 layers (tile tables index layers in 16
+    bits): the deepest allowed column is laid out, one more layer is refused
+    with SDG_E_MESH."""
+    vxy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    tri = np.array([[0, 1, 2]], dtype=np.int32)
+    nbr = np.full((1, 3), -1, dtype=np.int32)
+    for n, ok in ((65535, True), (65536, False)):
+        zlev = np.repeat(-np.arange(n + 1, dtype=np.float64)[:, None], 3, axis=1)
+        mesh = P.Mesh(vxy, tri, nbr, np.array([n], dtype=np.int32), zlev, 1)
+        if ok:
+            lay = mesh.layout()
+            assert lay.max_layers == n and lay.n_prisms == n and lay.n_slots == 64 * n
+        else:
+            assert _status(lambda: mesh.layout()) == -2
