@@ -140,3 +140,32 @@ def test_layer_count_limits():
             assert lay.max_layers == n and lay.n_prisms == n and lay.n_slots == 64 * n
         else:
             assert _status(lambda: mesh.layout()) == -2
+
+
+def test_slot_count_limit():
+    """The kernels address one field's six node rows with 32-bit byte offsets,
+    so a mesh is laid out only while 6 x n_slots x 8 bytes fits 32 bits
+    (89,478,485 slots, whatever the precision): 22 cells of 64 isolated
+    columns, one column per cell deep, are laid out at 89,478,464 slots and
+    refused with SDG_E_UNSUPPORTED at 89,478,528."""
+    n_cells = 22
+    C = 64 * n_cells
+    vxy = np.zeros((3 * C, 2))
+    for c in range(C):
+        x0, y0 = 2.0 * (c % 64), 2.0 * (c // 64)
+        vxy[3 * c:3 * c + 3] = [[x0, y0], [x0 + 1.0, y0], [x0, y0 + 1.0]]
+    tri = np.arange(3 * C, dtype=np.int32).reshape(C, 3)
+    nbr = np.full((C, 3), -1, dtype=np.int32)
+    for last, ok in ((21866, True), (21867, False)):
+        nl = np.ones(C, dtype=np.int32)
+        nl[::64] = 65535
+        nl[64 * (n_cells - 1)] = last
+        zlev = np.concatenate([np.repeat(-np.arange(n + 1, dtype=np.float64)[:, None], 3, axis=1) for n in nl])
+        slots = 64 * int(nl[::64].sum())
+        assert (6 * slots * 8 < 2 ** 32) == ok
+        for prec in (P.SDG_FP64, P.SDG_FP32_STATE_FP64_SOLVE):
+            mesh = P.Mesh(vxy, tri, nbr, nl, zlev, 1, prec)
+            if ok:
+                assert mesh.layout().n_slots == slots
+            else:
+                assert _status(lambda: mesh.layout()) == -5
