@@ -169,7 +169,9 @@ const char* sdg_last_error(void);
 /* Validate a mesh description and report sizes: columns grouped in cells of
  * 64, each as deep as its deepest column (the paper's section 2.1.1 cell
  * structure).  Host only; no GPU needed.  SDG_E_ARG / SDG_E_MESH with a
- * message on failure. */
+ * message on failure.  Limits: 1 to 65,535 layers per column (SDG_E_MESH
+ * beyond); at most 89,478,485 slots, since the kernels address one field's
+ * six node rows with 32-bit byte offsets (SDG_E_UNSUPPORTED beyond). */
 sdg_status sdg_query_layout(const sdg_mesh_desc* mesh, sdg_layout* out);
 
 /* Slot of each prism in natural order: host_slots[off[c] + l] for column c,
